@@ -1,0 +1,228 @@
+"""Pins for the oracle's operators: KB kernel, exact NDFT, gridding NUFFT.
+
+Each pin checks the oracle against something other than itself: numerical
+quadrature, numpy's FFT on on-grid samples, the adjoint identity, the unit
+sum-of-squares invariant, and the convergence of the NUFFT to the exact
+operator as the kernel widens.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import synth
+from oracle import kb, ndft, nufft
+
+
+# ---------------------------------------------------------------- KB kernel
+@pytest.mark.parametrize("alpha,W", [(2.0, 4), (1.25, 4), (1.25, 6), (2.0, 8)])
+def test_kb_ft_matches_quadrature(alpha, W):
+    beta = kb.kb_beta(alpha, W)
+    for nu in [0.0, 0.1, 0.25, 0.4]:
+        f = lambda u: kb.kb_kernel(np.array([u]), W, beta)[0] * math.cos(2 * math.pi * nu * u)
+        q, _ = integrate.quad(f, -W / 2, W / 2, epsabs=0, epsrel=1e-12, limit=200)
+        assert abs(q - kb.kb_ft(np.array([nu]), W, beta)[0]) <= 1e-9 * abs(q)
+
+
+def test_kb_edge_tap_is_zero_and_peak_positive():
+    beta = kb.kb_beta(1.25, 4)
+    v = kb.kb_kernel(np.array([-2.0, 2.0, 0.0, 1.999999]), 4, beta)
+    assert v[0] == 0.0 and v[1] == 0.0 and v[2] > v[3] > 0.0
+
+
+def test_grid_sizes_are_even_5_smooth():
+    assert kb.grid_size(160, 1.25) == 200
+    assert kb.grid_size(256, 1.25) == 320
+    assert kb.grid_size(128, 2.0) == 256
+    assert kb.grid_size(7, 2.0) == 16          # 14 -> 16? 14 = 2*7 is not 5-smooth
+    for n in range(2, 200, 2):
+        g = kb.grid_size(n, 1.25)
+        r = g
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        assert r == 1 and g % 2 == 0 and g >= 1.25 * n
+
+
+# ------------------------------------------------------------- exact NDFT
+def _rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("shape", [(8, 6), (4, 6, 8)])
+def test_ndft_on_grid_equals_numpy_fft(shape):
+    """Cartesian samples omega = 2 pi m / N: the NDFT is an FFT (centred)."""
+    rng = np.random.default_rng(0)
+    x = _rand_c(rng, shape)
+    grids = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    k = np.stack([(2 * math.pi * g.ravel() / n) for g, n in zip(grids, shape)], axis=1)
+    k = np.where(k >= math.pi, k - 2 * math.pi, k).astype(np.float32)
+    y = ndft.forward(x, None, k, shape)[0]
+    # centred index n = m - N//2 : x placed at positions n mod N
+    xs = np.fft.ifftshift(x) if all(n % 2 == 0 for n in shape) else None
+    F = np.fft.fftn(xs) / math.sqrt(np.prod(shape))
+    kk = np.asarray(k, np.float64)
+    idx = tuple(np.round(kk[:, a] * n / (2 * math.pi)).astype(int) % n for a, n in enumerate(shape))
+    # the float32 coordinates are within 1e-7 of the grid; tolerance covers it
+    np.testing.assert_allclose(y, F[idx], rtol=0, atol=2e-5 * np.abs(F).max())
+
+
+@pytest.mark.parametrize("shape,C", [((10, 12), 3), ((4, 6, 8), 2)])
+def test_ndft_adjoint_identity(shape, C):
+    rng = np.random.default_rng(1)
+    k = synth.random_coords(300, len(shape), rng)
+    maps = synth.coil_maps(shape, C, rng)
+    x = _rand_c(rng, shape)
+    y = _rand_c(rng, (C, 300))
+    lhs = np.vdot(ndft.forward(x, maps, k, shape), y)
+    rhs = np.vdot(x, ndft.adjoint(y, maps, k, shape))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+def test_ndft_matches_dense_matrix():
+    rng = np.random.default_rng(2)
+    shape = (4, 5, 6)
+    k = synth.random_coords(50, 3, rng)
+    maps = synth.coil_maps(shape, 2, rng)
+    x = _rand_c(rng, shape)
+    A = ndft.matrix(maps, k, shape)
+    np.testing.assert_allclose(ndft.forward(x, maps, k, shape).ravel(), A @ x.ravel(), rtol=1e-12, atol=1e-12)
+
+
+def test_sos_invariant_full_cartesian_is_identity():
+    """Unit sum-of-squares maps + full Cartesian sampling: A^H A = I."""
+    rng = np.random.default_rng(3)
+    shape = (8, 8)
+    maps = synth.coil_maps(shape, 4, rng)
+    np.testing.assert_allclose(np.sum(np.abs(maps) ** 2, axis=0), 1.0, rtol=0, atol=1e-14)
+    g = np.meshgrid(*[np.arange(n) - n // 2 for n in shape], indexing="ij")
+    k = np.stack([2 * math.pi * gi.ravel() / n for gi, n in zip(g, shape)], axis=1).astype(np.float64)
+    A = ndft.matrix(maps, k, shape)
+    np.testing.assert_allclose(A.conj().T @ A, np.eye(64), atol=1e-6)
+
+
+# --------------------------------------------------------- gridding NUFFT
+THRESH = {(2.0, 4): 1.3e-3, (1.25, 4): 1.4e-2, (2.0, 6): 2e-5, (1.25, 6): 9e-4, (2.0, 8): 4e-6}
+
+
+def test_nufft_converges_to_ndft():
+    rng = np.random.default_rng(0)
+    shape = (32, 32)
+    k = synth.random_coords(2000, 2, rng)
+    k[8:58] = 0.0                       # 50 samples exactly at the centre
+    x = _rand_c(rng, shape)
+    ye = ndft.forward(x, None, k, shape)
+    errs = {}
+    for (a, W), th in THRESH.items():
+        y = nufft.Nufft(k, shape, None, a, W).forward(x)
+        errs[(a, W)] = np.linalg.norm(y - ye) / np.linalg.norm(ye)
+        assert errs[(a, W)] < th, ((a, W), errs[(a, W)])
+    assert errs[(2.0, 8)] < errs[(2.0, 6)] < errs[(2.0, 4)]
+    assert errs[(1.25, 6)] < errs[(1.25, 4)]
+
+
+def test_nufft_3d_multicoil_matches_ndft():
+    rng = np.random.default_rng(4)
+    shape = (8, 10, 12)
+    k = synth.random_coords(500, 3, rng)
+    maps = synth.coil_maps(shape, 3, rng)
+    x = _rand_c(rng, shape)
+    op = nufft.Nufft(k, shape, maps, 2.0, 6)
+    ye = ndft.forward(x, maps, k, shape)
+    assert np.linalg.norm(op.forward(x) - ye) / np.linalg.norm(ye) < 2e-5
+    y = _rand_c(rng, (3, 500))
+    xe = ndft.adjoint(y, maps, k, shape)
+    assert np.linalg.norm(op.adjoint(y) - xe) / np.linalg.norm(xe) < 2e-5
+
+
+@pytest.mark.parametrize("shape,alpha,W", [((16, 20), 1.25, 4), ((6, 8, 10), 2.0, 4), ((12, 12), 2.0, 6)])
+def test_nufft_adjoint_identity(shape, alpha, W):
+    rng = np.random.default_rng(5)
+    k = synth.random_coords(400, len(shape), rng)
+    maps = synth.coil_maps(shape, 2, rng)
+    op = nufft.Nufft(k, shape, maps, alpha, W)
+    x = _rand_c(rng, shape)
+    y = _rand_c(rng, (2, 400))
+    lhs = np.vdot(op.forward(x), y)
+    rhs = np.vdot(x, op.adjoint(y))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+def test_g32_rule_matters():
+    """The float32 grid-coordinate rule changes the result by ~1e-4 (so the
+    GPU must follow it), while both stay within the NUFFT error of the NDFT."""
+    shape = (128, 128)
+    k = synth.radial_2d(64, 256)
+    rng = np.random.default_rng(6)
+    x = _rand_c(rng, shape)
+    op = nufft.Nufft(k, shape, None, 2.0, 4)
+    y32 = op.forward(x)
+    # the same NUFFT evaluated from float64 grid coordinates
+    g64 = np.asarray(k, np.float64) * (np.array(op.G) / (2 * math.pi)) + np.array(op.G) // 2
+    g64 = np.where(g64 < 0, g64 + np.array(op.G), g64)
+    g64 = np.where(g64 >= np.array(op.G), g64 - np.array(op.G), g64)
+    op64 = nufft.Nufft(k, shape, None, 2.0, 4)
+    op64.g = g64
+    op64.cell = np.floor(g64).astype(np.int64)
+    op64._taps = op64._make_taps()
+    y64 = op64.forward(x)
+    rel = np.linalg.norm(y32 - y64) / np.linalg.norm(y64)
+    assert 2e-5 < rel < 1e-3
+
+
+def test_canonical_coords_edge_cases():
+    G = (256, 200)
+    k = np.array([[0.0, 0.0], [-np.float32(math.pi), 0.0],
+                  [np.nextafter(np.float32(math.pi), np.float32(0)), math.pi / 2]], dtype=np.float32)
+    g = nufft.canonical_coords(k, G)
+    assert g[0, 0] == 128.0 and g[0, 1] == 100.0           # k = 0 sits at G/2
+    assert 0.0 <= g[1, 0] < 256.0                            # fl32(-pi) < -pi wraps
+    assert g[2, 1] == 150.0                                  # pi/2 -> G/4 + G/2 exactly
+    assert g.dtype == np.float32
+    with pytest.raises(ValueError):
+        nufft.canonical_coords(np.array([[10.0, 0.0]], np.float32), G)
+    with pytest.raises(ValueError):
+        nufft.canonical_coords(np.array([[np.nan, 0.0]], np.float32), G)
+
+
+def test_sort_by_bin_properties():
+    rng = np.random.default_rng(7)
+    G, B = (64, 40), (16, 8)
+    k = synth.random_coords(3000, 2, rng)
+    g = nufft.canonical_coords(k, G)
+    perm, off = nufft.sort_by_bin(g, G, B)
+    key, nb = nufft.bin_keys(g, G, B)
+    assert sorted(perm.tolist()) == list(range(3000))       # a permutation
+    ks = key[perm]
+    assert np.all(np.diff(ks) >= 0)                          # sorted by key
+    same = np.diff(ks) == 0
+    assert np.all(np.diff(perm)[same] > 0)                   # stable
+    assert off[0] == 0 and off[-1] == 3000 and len(off) == nb[0] * nb[1] + 1
+    for b in range(len(off) - 1):
+        assert np.all(ks[off[b]:off[b + 1]] == b)
+
+
+def test_tile_touch_lists_brute_force():
+    rng = np.random.default_rng(8)
+    G, B, W = (20, 24), (4, 8), 4
+    k = synth.random_coords(200, 2, rng)
+    g = nufft.canonical_coords(k, G)
+    off, ent = nufft.tile_touch_lists(g, G, B, W)
+    nb = (G[0] // B[0], G[1] // B[1])
+    cl = np.floor(g).astype(int)
+    for t0 in range(nb[0]):
+        for t1 in range(nb[1]):
+            want = []
+            for s in range(200):
+                hit = False
+                for a0 in range(W):
+                    for a1 in range(W):
+                        j0 = (cl[s, 0] - 1 + a0) % G[0]
+                        j1 = (cl[s, 1] - 1 + a1) % G[1]
+                        if j0 // B[0] == t0 and j1 // B[1] == t1:
+                            hit = True
+                if hit:
+                    want.append(s)
+            tid = t0 * nb[1] + t1
+            assert ent[off[tid]:off[tid + 1]].tolist() == want

@@ -1,0 +1,265 @@
+"""Pins for the oracle's preconditioner, wavelet, PDHG and unrolled gradient."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ndft, nufft, pdhg, precond, unrolled, wavelet
+
+
+def _rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _cartesian(shape):
+    g = np.meshgrid(*[np.arange(n) - n // 2 for n in shape], indexing="ij")
+    return np.stack([2 * math.pi * gi.ravel() / n for gi, n in zip(g, shape)], axis=1).astype(np.float32)
+
+
+# ---------------------------------------------------------- preconditioner
+@pytest.mark.parametrize("shape,C", [((6, 8), 3), ((4, 4, 6), 2)])
+def test_precond_efficient_equals_definition(shape, C):
+    rng = np.random.default_rng(0)
+    k = synth.random_coords(60, len(shape), rng)
+    maps = synth.coil_maps(shape, C, rng)
+    pd = precond.definition(maps, k, shape)
+    pe = precond.efficient_exact(maps, k, shape)
+    np.testing.assert_allclose(pe, pd, rtol=1e-10)
+    assert np.all(pd > 0)
+
+
+def test_precond_sc_closed_form_equals_definition():
+    rng = np.random.default_rng(1)
+    shape = (8, 10)
+    k = synth.random_coords(80, 2, rng)
+    np.testing.assert_allclose(precond.sc_closed_form(k, shape), precond.definition(None, k, shape)[0], rtol=1e-8)
+    np.testing.assert_allclose(precond.efficient_exact(None, k, shape)[0], precond.definition(None, k, shape)[0], rtol=1e-10)
+
+
+def test_precond_cartesian_is_one():
+    """Cartesian sampling: p = 1 for SC, and for MC with unit-SoS maps."""
+    shape = (6, 8)
+    k = _cartesian(shape)
+    np.testing.assert_allclose(precond.sc_closed_form(k, shape), 1.0, rtol=1e-6)
+    maps = synth.coil_maps(shape, 3, np.random.default_rng(2))
+    np.testing.assert_allclose(precond.efficient_exact(maps, k, shape), 1.0, rtol=1e-5)
+
+
+def test_precond_mc_single_unit_coil_equals_sc():
+    rng = np.random.default_rng(3)
+    shape = (8, 8)
+    k = synth.random_coords(50, 2, rng)
+    ones = np.ones((1,) + shape, np.complex128)
+    np.testing.assert_allclose(precond.efficient_exact(ones, k, shape), precond.efficient_exact(None, k, shape), rtol=1e-12)
+
+
+def test_precond_global_phase_invariance():
+    rng = np.random.default_rng(4)
+    shape = (6, 6)
+    k = synth.random_coords(40, 2, rng)
+    maps = synth.coil_maps(shape, 2, rng)
+    p1 = precond.efficient_exact(maps, k, shape)
+    p2 = precond.efficient_exact(maps * np.exp(1j * 0.7), k, shape)
+    np.testing.assert_allclose(p1, p2, rtol=1e-12)
+
+
+def test_precond_nufft_build_within_nufft_error():
+    rng = np.random.default_rng(5)
+    shape = (8, 10)
+    k = synth.random_coords(120, 2, rng)
+    maps = synth.coil_maps(shape, 3, rng)
+    pd = precond.definition(maps, k, shape)
+    pn = precond.efficient_nufft(maps, k, shape, 2.0, 6)
+    assert np.max(np.abs(pn - pd) / pd) < 1e-3
+    pn4 = precond.efficient_nufft(maps, k, shape, 1.25, 4)
+    assert np.max(np.abs(pn4 - pd) / pd) < 5e-2
+
+
+# ---------------------------------------------------------------- wavelet
+def test_db4_defining_identity():
+    h = wavelet.db4_filter()
+    assert len(h) == 8
+    xi = np.random.default_rng(0).uniform(-math.pi, math.pi, 50)
+    H = np.array([np.sum(h * np.exp(-1j * x * np.arange(8))) for x in xi])
+    y = np.sin(xi / 2) ** 2
+    P = 1 + 4 * y + 10 * y ** 2 + 20 * y ** 3
+    np.testing.assert_allclose(np.abs(H) ** 2, 2 * np.cos(xi / 2) ** 8 * P, rtol=1e-12, atol=1e-14)
+    assert abs(h[0]) > abs(h[-1])                       # minimum phase: energy first
+
+
+def test_db4_orthonormal_and_vanishing_moments():
+    h = wavelet.db4_filter()
+    g = wavelet.highpass(h)
+    for s in range(4):
+        v = np.sum(h[2 * s:] * h[:8 - 2 * s])
+        assert abs(v - (1.0 if s == 0 else 0.0)) < 1e-14
+    t = np.arange(8)
+    for m in range(4):
+        assert abs(np.sum(g * t ** m)) < 1e-9 * max(1, 8 ** m)
+    assert abs(np.sum(h) - math.sqrt(2)) < 1e-15
+
+
+@pytest.mark.parametrize("shape,levels", [((16,), 2), ((16, 8), 2), ((8, 8, 16), 2)])
+def test_wavelet_is_orthogonal(shape, levels):
+    n = int(np.prod(shape))
+    Wm = np.stack([wavelet.forward(np.eye(n)[i].reshape(shape), levels).ravel() for i in range(n)], axis=1)
+    np.testing.assert_allclose(Wm.T @ Wm, np.eye(n), atol=1e-13)
+    c = np.random.default_rng(1).standard_normal(shape)
+    np.testing.assert_allclose(wavelet.inverse(c, levels).ravel(), Wm.T @ c.ravel(), atol=1e-13)
+
+
+def test_wavelet_polynomial_has_zero_details():
+    """A cubic signal gives zero detail coefficients away from the wrap."""
+    x = (np.arange(64) / 64.0) ** 3
+    c = wavelet.forward(x, 1)
+    d = c[32:]
+    assert np.max(np.abs(d[:28])) < 1e-12
+
+
+def test_soft_threshold_cases():
+    v = np.array([0.0, 3 + 4j, 0.5j, -2.0])
+    out = wavelet.soft(v, 1.0)
+    np.testing.assert_allclose(out, [0.0, (3 + 4j) * 0.8, 0.0, -1.0])
+
+
+# ------------------------------------------------------------------- PDHG
+def _small_problem(C=3, seed=0, shape=(16, 16)):
+    rng = np.random.default_rng(seed)
+    k = synth.radial_2d(24, 32)
+    maps = synth.coil_maps(shape, C, rng)
+    x = synth.phantom(shape, rng)
+    op = nufft.Nufft(k, shape, maps, 2.0, 4)
+    y = op.forward(x) + synth.noise((C, k.shape[0]), 1e-3, rng)
+    return op, y, k, maps, x
+
+
+def test_power_method_matches_eigvalsh():
+    rng = np.random.default_rng(1)
+    shape = (6, 6)
+    k = synth.random_coords(40, 2, rng)
+    maps = synth.coil_maps(shape, 2, rng)
+    A = ndft.matrix(maps, k, shape)
+    p = precond.definition(maps, k, shape)
+    M = A.conj().T @ (p.ravel()[:, None] * A)
+    lam = np.linalg.eigvalsh(M)[-1]
+    f = lambda v: ndft.forward(v, maps, k, shape)
+    a = lambda u: ndft.adjoint(u, maps, k, shape)
+    est = pdhg.power_method(f, a, p, shape, 300)
+    assert abs(est - lam) < 1e-8 * lam
+    est30 = pdhg.power_method(f, a, p, shape, 30)
+    assert est30 <= lam * (1 + 1e-12) and est30 > 0.5 * lam
+    lam_i = np.linalg.eigvalsh(A.conj().T @ A)[-1]
+    assert abs(pdhg.power_method(f, a, None, shape, 300) - lam_i) < 1e-8 * lam_i
+    assert abs(lam_i - np.linalg.norm(A, 2) ** 2) < 1e-10 * lam_i
+
+
+def test_schedule_recursion():
+    s, t, th = pdhg.schedule(4.0, 0.25, 5)
+    assert s[0] == 1.0 and t[0] == 0.25
+    for i in range(4):
+        assert th[i] == 1.0 / (1.0 + 2.0 * s[i] * 0.25)
+        assert s[i + 1] == th[i] * s[i] and t[i + 1] == t[i] / th[i]
+    np.testing.assert_allclose(s * t, 0.25)
+
+
+def test_pdhg_l2_converges_to_cg_and_gap_closes():
+    op, y, k, maps, _ = _small_problem()
+    lam = 1e-3
+    shape = op.shape
+    xs, info = pdhg.cg_l2(op.forward, op.adjoint, y, shape, lam)
+    assert info == 0
+    # the fixed-point relation x* = -A^H (A x* - y) / lam (sign-corrected Supplement)
+    u_star = op.forward(xs) - y
+    np.testing.assert_allclose(xs, -op.adjoint(u_star) / lam, rtol=0, atol=1e-6 * np.abs(xs).max())
+    p = precond.efficient_nufft(maps, k, shape, 2.0, 4)
+    gaps = []
+    for iters in (50, 1500):
+        x, u, _ = pdhg.pdhg(op.forward, op.adjoint, y, p, shape, "l2", lam, iters)
+        gaps.append(pdhg.objective(op.forward, y, x, "l2", lam) - pdhg.dual_objective_l2(op.adjoint, y, u, lam))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-4
+    fx = pdhg.objective(op.forward, y, x, "l2", lam)
+    assert 0 <= gaps[1] < 1e-4 * fx and gaps[1] < 0.05 * gaps[0]
+
+
+def test_pdhg_preconditioning_beats_identity():
+    op, y, k, maps, _ = _small_problem(seed=1)
+    lam = 1e-3
+    shape = op.shape
+    xs, _ = pdhg.cg_l2(op.forward, op.adjoint, y, shape, lam)
+    fstar = pdhg.objective(op.forward, y, xs, "l2", lam)
+    res = {}
+    for name, p in [("I", None), ("SC", precond.efficient_nufft(None, k, shape, 2.0, 4)[0]),
+                    ("MC", precond.efficient_nufft(maps, k, shape, 2.0, 4))]:
+        h = []
+        pdhg.pdhg(op.forward, op.adjoint, y, p, shape, "l2", lam, 30, history=h)
+        res[name] = h[-1] - fstar
+        assert h[-1] < h[0]
+    assert res["SC"] < 0.1 * res["I"] and res["MC"] < 0.1 * res["I"]
+
+
+def test_pdhg_unitary_special_cases():
+    """One coil, full Cartesian, p = 1: closed-form minimisers."""
+    shape = (16, 16)
+    rng = np.random.default_rng(2)
+    k = _cartesian(shape)
+    y = _rand_c(rng, (1, 256))
+    f = lambda v: ndft.forward(v, None, k, shape)
+    a = lambda u: ndft.adjoint(u, None, k, shape)
+    ahy = a(y)
+    lam = 0.3
+    # float32 coordinates leave A unitary to ~1e-7, hence the 5e-6 bound
+    x, _, info = pdhg.pdhg(f, a, y, None, shape, "l2", lam, 100, accel=False)
+    np.testing.assert_allclose(x, ahy / (1 + lam), atol=5e-6)
+    xa, _, info = pdhg.pdhg(f, a, y, None, shape, "l2", lam, 1600)   # O(1/k^2) schedule
+    np.testing.assert_allclose(xa, ahy / (1 + lam), atol=2e-5)
+    lam1 = 0.05
+    x1, _, _ = pdhg.pdhg(f, a, y, None, shape, "l1wav", lam1, 200, levels=2, accel=False)
+    want = wavelet.inverse(wavelet.soft(wavelet.forward(ahy, 2), lam1), 2)
+    np.testing.assert_allclose(x1, want, atol=5e-6)
+
+
+# ------------------------------------------------------ unrolled gradients
+def test_unrolled_gradient_matches_finite_differences():
+    op, y, k, maps, xgt = _small_problem(C=2, seed=3, shape=(8, 8))
+    p = precond.efficient_nufft(maps, k, op.shape, 2.0, 4)
+    K = 4
+    sig = np.array([1.0, 0.8, 0.7, 0.6])
+    lmax = pdhg.power_method(op.forward, op.adjoint, p, op.shape, 30)
+    tau = np.array([0.5, 0.6, 0.7, 0.8]) / lmax
+    th = np.array([0.9, 0.8, 0.85, 0.7])
+    lam = 0.01
+    x0 = 0.1 * _rand_c(np.random.default_rng(9), op.shape)
+
+    def L(s, t, h, l, yy=y, xx=x0):
+        xK, _ = unrolled.forward(op.forward, op.adjoint, yy, p, s, t, h, l, op.shape, x0=xx, keep=False)
+        return unrolled.loss(xK, xgt)
+
+    xK, rec = unrolled.forward(op.forward, op.adjoint, y, p, sig, tau, th, lam, op.shape, x0=x0)
+    g = unrolled.backward(op.forward, op.adjoint, y, p, sig, tau, th, lam, rec, xK - xgt)
+    eps = 1e-6
+    for i in range(K):
+        e = np.zeros(K)
+        e[i] = eps
+        for name, base, fn in [("sigma", sig, lambda v: L(v, tau, th, lam)),
+                               ("tau", tau, lambda v: L(sig, v, th, lam)),
+                               ("theta", th, lambda v: L(sig, tau, v, lam))]:
+            h = eps * max(abs(base[i]), 1e-3)
+            ee = np.zeros(K)
+            ee[i] = h
+            fd = (fn(base + ee) - fn(base - ee)) / (2 * h)
+            assert abs(fd - g[name][i]) <= 1e-6 * max(1.0, abs(fd)), (name, i, fd, g[name][i])
+    h = eps * lam
+    fd = (L(sig, tau, th, lam + h) - L(sig, tau, th, lam - h)) / (2 * h)
+    assert abs(fd - g["lam"]) <= 1e-5 * max(1.0, abs(fd))
+    # complex inputs: directional derivatives along random directions
+    rng = np.random.default_rng(10)
+    for name, base, grad in [("y", y, g["y"]), ("x0", x0, g["x0"])]:
+        dv = _rand_c(rng, base.shape)
+        hh = 1e-6
+        if name == "y":
+            fd = (L(sig, tau, th, lam, yy=y + hh * dv) - L(sig, tau, th, lam, yy=y - hh * dv)) / (2 * hh)
+        else:
+            fd = (L(sig, tau, th, lam, xx=x0 + hh * dv) - L(sig, tau, th, lam, xx=x0 - hh * dv)) / (2 * hh)
+        an = float(np.vdot(grad, dv).real)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, fd, an)
