@@ -1,0 +1,209 @@
+/*
+ * kpdhg.h - C ABI of the MI355X (gfx950) hot path of k-space-preconditioned
+ * PDHG reconstruction for non-Cartesian multi-coil MRI (Ong, Uecker, Lustig,
+ * "Accelerating Non-Cartesian MRI Reconstruction Convergence using k-space
+ * Preconditioning").
+ *
+ * Conventions for every call
+ * --------------------------
+ *  - Pointers are DEVICE pointers unless a parameter says "host".
+ *  - complex values are interleaved float pairs (re, im) == torch.complex64.
+ *  - An image has shape (N_0, .., N_{d-1}), C order, last axis fastest; array
+ *    index m_a sits at the centred position n_a = m_a - N_a/2.
+ *  - k-space arrays are coil-major [C][M] in the caller's sample order
+ *    (Problem Setup: the stacked vector y of Eq. model).
+ *  - Coordinates are float32 [M][d] in radians per pixel, nominally in
+ *    [-pi, pi); column a pairs with image axis a.  omega = 2 pi f / N_a with
+ *    the paper's f in cycles.  Values up to about 3 pi are wrapped
+ *    periodically; anything further out, NaN or inf is rejected by
+ *    nufft_plan with KP_ERR_INVALID_ARG.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    stream-ordered and asynchronous unless its comment says otherwise.  A
+ *    plan serves one stream at a time and is not re-entrant.
+ *  - Every call returns KP_OK or a negative status and never throws; the
+ *    message of the last failure on the calling thread is kp_last_error().
+ *    Asynchronous kernel faults surface as KP_ERR_HIP at the next checked
+ *    call.
+ *  - Memory: nufft_plan allocates every workspace the plan's forward,
+ *    adjoint and solve calls need; those calls never allocate.
+ *    precond_build allocates and frees its own scratch (setup-time call).
+ */
+#ifndef KPDHG_H
+#define KPDHG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kp_plan* kp_plan_t;
+
+enum {
+    KP_OK = 0,
+    KP_ERR_INVALID_ARG = -1,  /* bad pointer, size, option or coordinate   */
+    KP_ERR_UNSUPPORTED = -2,  /* valid but outside what the kernels cover  */
+    KP_ERR_OOM = -3,          /* device or host allocation failed          */
+    KP_ERR_HIP = -4           /* a HIP runtime call or kernel failed       */
+};
+
+enum { KP_PRECOND_NONE = 0, KP_PRECOND_SC = 1, KP_PRECOND_MC = 2 };
+enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1 };
+
+/* Kernel tiling.  Zeros select the built-in choice for the shape. */
+typedef struct {
+    int bin_size[3];   /* spreading/binning tile edge per axis; must divide G_a */
+    int max_chunk;     /* max touch-list entries per spreading work item        */
+} kp_tuning;
+
+/* Shape facts of a plan (filled by nufft_plan_info, host struct). */
+typedef struct {
+    int ndim;
+    int64_t shape[3];
+    int64_t grid[3];        /* oversampled grid G_a                           */
+    int64_t ncoils, nsamples;
+    int kb_width;
+    float oversamp;
+    double kb_beta;         /* Kaiser-Bessel shape parameter                  */
+    int bin_size[3];
+    int64_t nbins;          /* number of tiles                                */
+    int64_t ntouch;         /* total tile-touch entries                       */
+    int64_t nwork;          /* spreading work items                           */
+    int64_t heavy_tiles;    /* tiles split over several work items            */
+    int64_t workspace_bytes;/* device bytes owned by the plan                 */
+} kp_plan_info;
+
+/* PDHG options (host struct). */
+typedef struct {
+    int reg;              /* KP_REG_L2 or KP_REG_L1_WAVELET                          */
+    float lambda;         /* regularisation weight (Problem Setup, Eq. obj)          */
+    int iters;            /* PDHG iterations K >= 1                                  */
+    int wavelet_levels;   /* db4 levels for KP_REG_L1_WAVELET (every N_a % 2^L == 0) */
+    float lambda_max;     /* <= 0: estimate lambda_max(P A A^H) by the power method  */
+    int power_iters;      /* power-method iterations (the paper uses 30)             */
+    float sigma0;         /* sigma^(0) (the paper fixes 1)                           */
+    int accel;            /* 1: theta_k = 1/(1+2 sigma_k min p) schedule; 0: theta=1 */
+    const void* x0;       /* NULL or c64 [N] initial primal                          */
+    const void* u0;       /* NULL or c64 [C][M] initial dual (caller order)          */
+    double* objective_host; /* NULL or host double [iters+1]: 1/2||Ax-y||^2 + g(x)
+                               before the first and after every iteration; costs one
+                               extra forward and a host sync per iteration           */
+    float* lambda_max_out;  /* NULL or device float [1]: the lambda_max used          */
+} kp_pdhg_opts;
+
+/* Build a plan: canonical float32 grid coordinates, bin keys, a stable
+ * bit-exact sort of samples by tile, tile touch lists, Kaiser-Bessel and
+ * deapodisation tables, twiddles, and every workspace.
+ *   ndim       2 or 3
+ *   shape      host int64[ndim], each N_a even, 2 <= N_a <= 4096
+ *   ncoils     C >= 1 (maps == NULL requires C == 1: unit sensitivity)
+ *   nsamples   M >= 1
+ *   coords     device float32 [M][ndim]; copied (in sorted order) by the plan
+ *   maps       device c64 [C][N] coil sensitivities (Problem Setup, s_c), or
+ *              NULL; copied by the plan (the caller may free its copy once
+ *              the stream has passed this call)
+ *   oversamp   alpha in [1.25, 2]; G_a = ceil(alpha N_a) raised to the next
+ *              even 5-smooth integer (Experiments: alpha = 1.25)
+ *   kb_width   W in {2, 4, 6, 8} (Experiments: W = 4); Kaiser-Bessel shape
+ *              beta of Beatty et al.
+ *   tuning     host struct or NULL
+ * Synchronises `stream` once (to size the spreading work list). */
+int nufft_plan(kp_plan_t* out, int ndim, const int64_t* shape, int64_t ncoils,
+               int64_t nsamples, const float* coords, const void* maps,
+               float oversamp, int kb_width, const kp_tuning* tuning, void* stream);
+
+/* y = A x  (Problem Setup, Eq. model_i without noise; NUFFT approximation):
+ * coil multiply, deapodisation, zero-padded oversampled FFT, Kaiser-Bessel
+ * interpolation.  x: c64 [N]; y: c64 [C][M] in the caller's sample order,
+ * overwritten. */
+int nufft_forward(kp_plan_t plan, const void* x, void* y, void* stream);
+
+/* x = A^H y: Kaiser-Bessel spreading accumulated per tile in LDS, inverse
+ * oversampled FFT, crop, deapodisation, conj(s_c) and coil sum.
+ * y: c64 [C][M] caller order; x: c64 [N], overwritten. */
+int nufft_adjoint(kp_plan_t plan, const void* y, void* x, void* stream);
+
+/* l2-optimised diagonal k-space preconditioner (section "l2 optimized
+ * diagonal k-space preconditioners", Appendix A) built with the efficient
+ * algorithm of "Efficient computation of the multi-channel preconditioner"
+ * (Fig. 2): autocorrelations of s_c s_d^* by FFT at 2N, the point-spread
+ * function by an adjoint NUFFT of ones on the 2N image, a forward NUFFT of
+ * their product, p = 1/Re(.).
+ *   kind KP_PRECOND_SC: Eq. sc_precond (coil maps ignored), p float [M]
+ *   kind KP_PRECOND_MC: Eq. mc_precond, p float [C][M]
+ * Caller sample order.  Allocates and frees scratch; synchronises. */
+int precond_build(kp_plan_t plan, int kind, float* p, void* stream);
+
+/* lambda_max(P A A^H) by the power method on A^H P A (Experiments: 30
+ * iterations): v0 = ones/||ones||, v <- A^H P A v / ||A^H P A v||; the
+ * estimate is the last norm.  p: NULL (P = I), float [M] (SC) or [C][M]
+ * (MC) per p_kind.  out: device float [1].  No host sync. */
+int pdhg_lambda_max(kp_plan_t plan, const float* p, int p_kind, int iters,
+                    float* out, void* stream);
+
+/* Preconditioned PDHG for simple regularisers (section "Preconditioned PDHG
+ * for simple regularizers"): per iteration
+ *   u  <- (u + sigma P (A xbar - y)) / (1 + sigma P)   (fused in interpolation)
+ *   x' <- prox_{tau g}(x - tau A^H u)                   (fused in the last IFFT pass)
+ *   xbar <- x' + theta (x' - x)
+ * with sigma_0 = opts->sigma0, tau_0 = 1/(sigma_0 lambda_max) and the
+ * accelerated schedule theta_k = 1/(1 + 2 sigma_k min p), sigma_{k+1} =
+ * theta_k sigma_k, tau_{k+1} = tau_k/theta_k (or theta = 1 if !accel).
+ * g = lambda||x||^2/2 (prox z/(1+tau lambda)) or lambda||W x||_1 with the
+ * periodised db4 W (prox W^H soft(W z, tau lambda)).  x0 = u0 = 0 unless
+ * given.  y: c64 [C][M]; p: NULL / float [M] / float [C][M] per p_kind;
+ * x_out: c64 [N]; u_out: NULL or c64 [C][M] (caller order).  No host sync
+ * unless opts->objective_host is set. */
+int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind,
+               const kp_pdhg_opts* opts, void* x_out, void* u_out, void* stream);
+
+/* Unrolled differentiable l2 PDHG (same iteration as pdhg_solve, with free
+ * per-step sizes): params = device float [3K+1] = sigma[K], tau[K],
+ * theta[K], lambda.  Forward: runs K steps from x0 (NULL = 0), u0 = 0,
+ * writes x_K and stores checkpoints of (x, xbar, u) every `ckpt_every`
+ * steps into `ckpt` (device, size pdhg_unrolled_ckpt_bytes).
+ * Backward: given g_x = dL/dx_K (PyTorch's complex gradient convention),
+ * recomputes each segment from its checkpoint and runs the reverse
+ * recursion; writes g_params float [3K+1], g_y c64 [C][M] (or NULL) and
+ * g_x0 c64 [N] (or NULL).  Both use the plan's NUFFT kernels for A and A^H. */
+int64_t pdhg_unrolled_ckpt_bytes(kp_plan_t plan, int K, int ckpt_every);
+int pdhg_unrolled_forward(kp_plan_t plan, const void* y, const float* p, int p_kind,
+                          const float* params, int K, int ckpt_every, const void* x0,
+                          void* x_out, void* ckpt, void* stream);
+int pdhg_unrolled_backward(kp_plan_t plan, const void* y, const float* p, int p_kind,
+                           const float* params, int K, int ckpt_every, const void* x0,
+                           const void* ckpt, const void* g_x, float* g_params,
+                           void* g_y, void* g_x0, void* stream);
+
+/* Release a plan after synchronising its last stream.  NULL is ignored. */
+void nufft_destroy(kp_plan_t plan);
+
+/* Host struct with the plan's sizes. */
+int nufft_plan_info(kp_plan_t plan, kp_plan_info* info);
+
+/* Copy the plan's sort to caller buffers (device int32): perm [M] (sorted
+ * position -> caller sample index), bin_offsets [nbins+1], touch_offsets
+ * [nbins+1] and touch [ntouch] (sorted sample positions, ascending within a
+ * tile).  Any pointer may be NULL. */
+int nufft_plan_sort(kp_plan_t plan, int32_t* perm, int32_t* bin_offsets,
+                    int32_t* touch_offsets, int32_t* touch, void* stream);
+
+/* Canonical float32 grid coordinates g [M][ndim] in caller order. */
+int nufft_plan_grid_coords(kp_plan_t plan, float* g, void* stream);
+
+/* The periodised db4 analysis filter h[8] derived by the library (host). */
+int kp_db4_filter(double* h8);
+
+/* Host-side argument validation only (no device work): returns the status
+ * nufft_plan would return for these arguments before touching the device. */
+int nufft_plan_validate(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples,
+                        const void* coords, const void* maps, float oversamp, int kb_width,
+                        const kp_tuning* tuning);
+
+/* Thread-local message of the last failure (valid until the next call). */
+const char* kp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPDHG_H */

@@ -1,0 +1,197 @@
+"""MI355X-native hot path of k-space-preconditioned PDHG (Ong, Uecker, Lustig).
+
+Python binding over the C ABI of libkpdhg (include/kpdhg.h), with the same
+function names.  Tensors are torch tensors on the GPU (complex64 / float32);
+each call runs on torch's current HIP stream.  The binding only marshals
+arguments; every computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVELET, KP_REG_L2,
+                   KpError, PdhgOpts, PlanInfo, Tuning)
+
+__all__ = [
+    "Plan", "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
+    "pdhg_solve", "nufft_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
+    "KP_REG_L2", "KP_REG_L1_WAVELET",
+]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    return t.contiguous()
+
+
+class Plan:
+    """A NUFFT plan (owns the library handle); see nufft_plan."""
+
+    def __init__(self, handle, shape, ncoils, nsamples, device):
+        self.handle = handle
+        self.shape = tuple(shape)
+        self.ncoils = int(ncoils)
+        self.nsamples = int(nsamples)
+        self.device = device
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _lib.check(_lib.load().nufft_plan_info(self.handle, ctypes.byref(inf)))
+        d = inf.ndim
+        return {
+            "ndim": d, "shape": tuple(inf.shape[:d]), "grid": tuple(inf.grid[:d]),
+            "ncoils": inf.ncoils, "nsamples": inf.nsamples, "kb_width": inf.kb_width,
+            "oversamp": inf.oversamp, "kb_beta": inf.kb_beta, "bin_size": tuple(inf.bin_size[:d]),
+            "nbins": inf.nbins, "ntouch": inf.ntouch, "nwork": inf.nwork,
+            "heavy_tiles": inf.heavy_tiles, "workspace_bytes": inf.workspace_bytes,
+        }
+
+    def sort(self):
+        """(perm, bin_offsets, touch_offsets, touch) as int32 device tensors."""
+        inf = self.info()
+        dev = self.device
+        perm = torch.empty(self.nsamples, dtype=torch.int32, device=dev)
+        boff = torch.empty(inf["nbins"] + 1, dtype=torch.int32, device=dev)
+        toff = torch.empty(inf["nbins"] + 1, dtype=torch.int32, device=dev)
+        touch = torch.empty(max(inf["ntouch"], 1), dtype=torch.int32, device=dev)
+        _lib.check(_lib.load().nufft_plan_sort(self.handle, _ptr(perm), _ptr(boff), _ptr(toff), _ptr(touch), _stream()))
+        return perm, boff, toff, touch[: inf["ntouch"]]
+
+    def grid_coords(self):
+        g = torch.empty((self.nsamples, len(self.shape)), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().nufft_plan_grid_coords(self.handle, _ptr(g), _stream()))
+        return g
+
+    def close(self):
+        if self.handle:
+            _lib.load().nufft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nufft_plan(coords, shape, maps=None, oversamp=1.25, kb_width=4, bin_size=None, max_chunk=0) -> Plan:
+    """Plan for coordinates [M][d] (float32, rad/pixel) and maps [C][*shape] (complex64)."""
+    L = _lib.load()
+    coords = _dev(coords, torch.float32, "coords")
+    shape = tuple(int(n) for n in shape)
+    d = len(shape)
+    if coords.dim() != 2 or coords.shape[1] != d:
+        raise ValueError("coords must have shape [M, %d]" % d)
+    C = 1
+    if maps is not None:
+        maps = _dev(maps, torch.complex64, "maps")
+        C = maps.shape[0]
+        if tuple(maps.shape[1:]) != shape:
+            raise ValueError("maps must have shape [C, *shape]")
+    tun = None
+    if bin_size is not None or max_chunk:
+        tun = Tuning()
+        for a in range(3):
+            tun.bin_size[a] = int(bin_size[a]) if bin_size is not None and a < d else 0
+        tun.max_chunk = int(max_chunk)
+    h = ctypes.c_void_p()
+    shp = (ctypes.c_int64 * d)(*shape)
+    _lib.check(L.nufft_plan(ctypes.byref(h), d, shp, C, coords.shape[0], _ptr(coords), _ptr(maps),
+                            float(oversamp), int(kb_width), ctypes.byref(tun) if tun is not None else None,
+                            _stream()))
+    return Plan(h, shape, C, coords.shape[0], coords.device)
+
+
+def nufft_forward(plan: Plan, x, out=None):
+    x = _dev(x, torch.complex64, "x")
+    if out is None:
+        out = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device)
+    _lib.check(_lib.load().nufft_forward(plan.handle, _ptr(x), _ptr(out), _stream()))
+    return out
+
+
+def nufft_adjoint(plan: Plan, y, out=None):
+    y = _dev(y, torch.complex64, "y")
+    if out is None:
+        out = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
+    _lib.check(_lib.load().nufft_adjoint(plan.handle, _ptr(y), _ptr(out), _stream()))
+    return out
+
+
+def precond_build(plan: Plan, kind):
+    n = (plan.nsamples,) if kind == KP_PRECOND_SC else (plan.ncoils, plan.nsamples)
+    p = torch.empty(n, dtype=torch.float32, device=plan.device)
+    _lib.check(_lib.load().precond_build(plan.handle, int(kind), _ptr(p), _stream()))
+    return p
+
+
+def _p_kind(p):
+    if p is None:
+        return KP_PRECOND_NONE
+    return KP_PRECOND_SC if p.dim() == 1 else KP_PRECOND_MC
+
+
+def pdhg_lambda_max(plan: Plan, p=None, iters=30):
+    out = torch.empty(1, dtype=torch.float32, device=plan.device)
+    if p is not None:
+        p = _dev(p, torch.float32, "p")
+    _lib.check(_lib.load().pdhg_lambda_max(plan.handle, _ptr(p), _p_kind(p), int(iters), _ptr(out), _stream()))
+    return out
+
+
+def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_levels=4, lambda_max=0.0,
+               power_iters=30, sigma0=1.0, accel=True, x0=None, u0=None, objective=False, want_u=False,
+               lambda_max_out=None):
+    """Run the preconditioned PDHG.  Returns x (and u, objective history when asked)."""
+    y = _dev(y, torch.complex64, "y")
+    if p is not None:
+        p = _dev(p, torch.float32, "p")
+    o = PdhgOpts()
+    o.reg = KP_REG_L2 if reg == "l2" else KP_REG_L1_WAVELET
+    o.lam = float(lam)
+    o.iters = int(iters)
+    o.wavelet_levels = int(wavelet_levels)
+    o.lambda_max = float(lambda_max)
+    o.power_iters = int(power_iters)
+    o.sigma0 = float(sigma0)
+    o.accel = 1 if accel else 0
+    if x0 is not None:
+        x0 = _dev(x0, torch.complex64, "x0")
+    if u0 is not None:
+        u0 = _dev(u0, torch.complex64, "u0")
+    o.x0 = _ptr(x0).value
+    o.u0 = _ptr(u0).value
+    hist = None
+    if objective:
+        hist = (ctypes.c_double * (iters + 1))()
+        o.objective_host = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    if lambda_max_out is not None:
+        o.lambda_max_out = lambda_max_out.data_ptr()
+    x = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
+    u = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device) if want_u else None
+    _lib.check(_lib.load().pdhg_solve(plan.handle, _ptr(y), _ptr(p), _p_kind(p), ctypes.byref(o), _ptr(x), _ptr(u),
+                                      _stream()))
+    out = [x]
+    if want_u:
+        out.append(u)
+    if objective:
+        out.append([hist[i] for i in range(iters + 1)])
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def nufft_destroy(plan: Plan):
+    plan.close()

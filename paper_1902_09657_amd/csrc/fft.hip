@@ -1,0 +1,294 @@
+// LDS-staged mixed-radix Stockham FFT passes for the oversampled NUFFT grid.
+//
+// One pass transforms every line of a [O][L][I] view along its middle axis
+// (I contiguous).  A workgroup stages `Ob x Ib` columns of length L in LDS,
+// runs the Stockham stages (radices 2, 3, 4, 5, 8; twiddles exp(-2 pi i m/L)
+// from a float table built in double precision on the host) between two LDS
+// buffers, and writes the result back.  Pruning: a forward pass reads only the
+// N non-zero input rows (centred placement n mod L, the zero rows are never
+// read) and an adjoint pass writes only the N kept output rows (centred crop).
+//
+// The first forward pass along the last image axis fuses the pre-pass of the
+// NUFFT (coil multiply x s_c, deapodisation 1/(sqrt(N) Chat), and the sign
+// (-1)^n that centres the spectrum so grid cell G/2 is k = 0); the last
+// adjoint pass fuses the mirror post-pass (conj(s_c), deapodisation, sign,
+// coil sum) and, optionally, the PDHG primal update.
+#include <algorithm>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ float2 rot(float2 a, int inv) {
+    return inv ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// cos(2 pi/5) = (sqrt5 - 1)/4, cos(4 pi/5) = -(sqrt5 + 1)/4,
+// sin(2 pi/5) = sqrt(10 + 2 sqrt5)/4, sin(4 pi/5) = sqrt(10 - 2 sqrt5)/4,
+// sin(2 pi/3) = sqrt3/2, cos(pi/4) = sqrt2/2
+#define KP_C51 0.30901699437494742f
+#define KP_C52 -0.80901699437494742f
+#define KP_S51 0.95105651629515357f
+#define KP_S52 0.58778525229247313f
+#define KP_S3 0.86602540378443865f
+#define KP_R2 0.70710678118654752f
+
+__device__ __forceinline__ void dft2(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+__device__ __forceinline__ void dft3(float2* v, int inv) {
+    float2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    float2 m = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+    float2 r = rot(cscale(t2, KP_S3), inv);  // -i s t2 (forward)
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+__device__ __forceinline__ void dft4(float2* v, int inv) {
+    float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    float2 b0 = cadd(v[1], v[3]), b1 = rot(csub(v[1], v[3]), inv);
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, b1);
+    v[3] = csub(a1, b1);
+}
+__device__ __forceinline__ void dft5(float2* v, int inv) {
+    float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    float2 b1 = make_float2(v[0].x + KP_C51 * t1.x + KP_C52 * t2.x, v[0].y + KP_C51 * t1.y + KP_C52 * t2.y);
+    float2 b2 = make_float2(v[0].x + KP_C52 * t1.x + KP_C51 * t2.x, v[0].y + KP_C52 * t1.y + KP_C51 * t2.y);
+    float2 d1 = make_float2(KP_S51 * t3.x + KP_S52 * t4.x, KP_S51 * t3.y + KP_S52 * t4.y);
+    float2 d2 = make_float2(KP_S52 * t3.x - KP_S51 * t4.x, KP_S52 * t3.y - KP_S51 * t4.y);
+    float2 r1 = rot(d1, inv), r2 = rot(d2, inv);  // -i d (forward)
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(b1, r1);
+    v[4] = csub(b1, r1);
+    v[2] = cadd(b2, r2);
+    v[3] = csub(b2, r2);
+}
+__device__ __forceinline__ void dft8(float2* v, int inv) {
+    // radix-2 split into two 4-point DFTs of even and odd samples
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft4(e, inv);
+    dft4(o, inv);
+    // twiddles w8^k, w8 = exp(-+ 2 pi i / 8)
+    float s = inv ? 1.f : -1.f;
+    float2 w1 = make_float2(KP_R2, s * KP_R2);
+    float2 w3 = make_float2(-KP_R2, s * KP_R2);
+    float2 o1 = cmul(o[1], w1);
+    float2 o2 = rot(o[2], inv);
+    float2 o3 = cmul(o[3], w3);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+__device__ __forceinline__ void dft_r(int R, float2* v, int inv) {
+    switch (R) {
+        case 2: dft2(v); break;
+        case 3: dft3(v, inv); break;
+        case 4: dft4(v, inv); break;
+        case 5: dft5(v, inv); break;
+        default: dft8(v, inv); break;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fft_pass(FftPass p) {
+    extern __shared__ float2 lds[];
+    const int ncol = p.Ob * p.Ib;
+    const int L = p.L;
+    float2* b0 = lds;
+    float2* b1 = lds + (size_t)L * ncol;
+    const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
+    const int64_t bid = blockIdx.x;
+    const int64_t o0 = (bid / nIb) * p.Ob;
+    const int64_t i0 = (bid % nIb) * p.Ib;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const float xs = p.xscale ? *p.xscale : 1.f;
+
+    // ---- load (pruned: only the Lin input rows are read)
+    if (p.pad_in) {
+        const int gap = L - p.Lin;
+        const int r0 = p.Lin / 2;
+        for (int idx = tid; idx < gap * ncol; idx += nt) {
+            int row = r0 + idx / ncol, col = idx % ncol;
+            b0[row * ncol + col] = make_float2(0.f, 0.f);
+        }
+    }
+    for (int idx = tid; idx < p.Lin * ncol; idx += nt) {
+        const int r = idx / ncol, col = idx % ncol;
+        const int64_t o = o0 + col / p.Ib, i = i0 + col % p.Ib;
+        float2 v = make_float2(0.f, 0.f);
+        if (o < p.O && i < p.I) {
+            if (p.pre == PRE_NONE) {
+                v = p.in[o * p.in_os + r * p.in_rs + i];
+            } else if (p.pre == PRE_MAPS) {
+                const int64_t e = o * p.Lin + r;
+                const float f = p.fo[o] * p.fr[r] * xs;
+                v = cscale(cmul(p.px[e], p.pmaps[e * p.I + i]), f);
+            } else {
+                const int64_t e = o * p.Lin + r;
+                const float f = p.fo[o] * p.fr[r] * xs;
+                v = cscale(p.px[e * p.I + i], f);
+            }
+        }
+        const int pos = p.pad_in ? (r - p.Lin / 2 + L) % L : r;
+        b0[pos * ncol + col] = v;
+    }
+    __syncthreads();
+
+    // ---- Stockham stages
+    float2* src = b0;
+    float2* dst = b1;
+    int Ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        const int R = p.rad[s];
+        const int nbf = L / R;
+        const int stride = L / (Ns * R);
+        for (int b = tid; b < nbf * ncol; b += nt) {
+            const int col = b % ncol, j = b / ncol;
+            const int k = j % Ns;
+            float2 v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (t < R) v[t] = src[(j + t * nbf) * ncol + col];
+            if (Ns > 1) {
+#pragma unroll
+                for (int t = 1; t < 8; ++t) {
+                    if (t < R) {
+                        float2 w = p.tw[t * k * stride];
+                        if (p.inverse) w.y = -w.y;
+                        v[t] = cmul(v[t], w);
+                    }
+                }
+            }
+            dft_r(R, v, p.inverse);
+            const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (t < R) dst[(base + t * Ns) * ncol + col] = v[t];
+        }
+        __syncthreads();
+        float2* tmp = src;
+        src = dst;
+        dst = tmp;
+        Ns *= R;
+    }
+
+    // ---- store (pruned: only the Lout kept rows are written)
+    if (p.post == POST_MAPS) {
+        // columns of one outer are the C coils: reduce conj(s_c) v_c over c
+        const int C = p.Ib;
+        for (int idx = tid; idx < p.Ob * p.Lout; idx += nt) {
+            const int ol = idx / p.Lout, m = idx % p.Lout;
+            const int64_t o = o0 + ol;
+            if (o >= p.O) continue;
+            const int q = p.crop_out ? (m - p.Lout / 2 + L) % L : m;
+            const int64_t e = o * p.Lout + m;
+            const float2* mp = p.qmaps + e * C;
+            const float2* row = src + q * ncol + ol * C;
+            float2 acc = make_float2(0.f, 0.f);
+            for (int c = 0; c < C; ++c) acc = cadd(acc, cmulc(row[c], mp[c]));
+            acc = cscale(acc, p.fo[o] * p.fr[m]);
+            if (p.epi == EPI_STORE) {
+                p.qx[e] = acc;
+            } else if (p.epi == EPI_L2) {
+                const float tau = *p.e_tau, th = *p.e_theta;
+                const float2 xo = p.ex[e];
+                const float den = 1.f / (1.f + tau * p.e_lambda);
+                const float2 xn = make_float2((xo.x - tau * acc.x) * den, (xo.y - tau * acc.y) * den);
+                p.exbar[e] = make_float2(xn.x + th * (xn.x - xo.x), xn.y + th * (xn.y - xo.y));
+                p.ex[e] = xn;
+            } else {  // EPI_Z: z = x - tau A^H u
+                const float tau = *p.e_tau;
+                const float2 xo = p.ex[e];
+                p.exbar[e] = make_float2(xo.x - tau * acc.x, xo.y - tau * acc.y);
+            }
+        }
+        return;
+    }
+    for (int idx = tid; idx < p.Lout * ncol; idx += nt) {
+        const int m = idx / ncol, col = idx % ncol;
+        const int64_t o = o0 + col / p.Ib, i = i0 + col % p.Ib;
+        if (o >= p.O || i >= p.I) continue;
+        const int q = p.crop_out ? (m - p.Lout / 2 + L) % L : m;
+        float2 v = src[q * ncol + col];
+        if (p.post == POST_NONE) {
+            p.out[o * p.out_os + m * p.out_rs + i] = v;
+        } else {  // POST_CHAN
+            const int64_t e = o * p.Lout + m;
+            p.qx[e * p.I + i] = cscale(v, p.fo[o] * p.fr[m]);
+        }
+    }
+}
+
+void fft_factor(int L, int* nst, int* rad) {
+    int n = 0, r = L;
+    while (r % 8 == 0 && r > 8 && n < kMaxStages) { rad[n++] = 8; r /= 8; }
+    while (r % 4 == 0 && n < kMaxStages) { rad[n++] = 4; r /= 4; }
+    while (r % 2 == 0 && n < kMaxStages) { rad[n++] = 2; r /= 2; }
+    while (r % 5 == 0 && n < kMaxStages) { rad[n++] = 5; r /= 5; }
+    while (r % 3 == 0 && n < kMaxStages) { rad[n++] = 3; r /= 3; }
+    if (r == 8 && n < kMaxStages) { rad[n++] = 8; r = 1; }
+    if (r != 1) fail(KP_ERR_UNSUPPORTED, "FFT length " + std::to_string(L) + " is not 5-smooth");
+    *nst = n;
+}
+
+size_t fft_lds_bytes(int L, int ncol) { return (size_t)2 * L * ncol * sizeof(float2); }
+
+static int lds_limit() {
+    static int lim = -1;
+    if (lim < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            lim = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+        else
+            lim = 65536;
+        (void)hipFuncSetAttribute((const void*)k_fft_pass, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipGetLastError();
+    }
+    return lim;
+}
+
+void launch_fft_pass(const FftPass& pin, hipStream_t s) {
+    FftPass p = pin;
+    const int lim = lds_limit();
+    // shrink the column block until both LDS buffers fit
+    while (fft_lds_bytes(p.L, p.Ob * p.Ib) > (size_t)lim) {
+        if (p.Ob > 1)
+            p.Ob = (p.Ob + 1) / 2;
+        else if (p.post != POST_MAPS && p.Ib > 1)
+            p.Ib = (p.Ib + 1) / 2;
+        else
+            fail(KP_ERR_UNSUPPORTED, "FFT line of length " + std::to_string(p.L) + " does not fit in LDS");
+    }
+    const size_t lds = fft_lds_bytes(p.L, p.Ob * p.Ib);
+    const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
+    const int64_t nOb = (p.O + p.Ob - 1) / p.Ob;
+    const int64_t nblk = nIb * nOb;
+    if (nblk <= 0) return;
+    if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "FFT pass grid too large");
+    hipLaunchKernelGGL(k_fft_pass, dim3((unsigned)nblk), dim3(256), lds, s, p);
+    KP_LAUNCH_CHECK();
+}
+
+}  // namespace kp

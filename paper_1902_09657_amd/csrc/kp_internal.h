@@ -1,0 +1,258 @@
+// Internal declarations shared by the translation units of libkpdhg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/kpdhg.h"
+
+namespace kp {
+
+// ----------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_error(const std::string& msg);
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+#define KP_HIP(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            ::kp::fail(KP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define KP_LAUNCH_CHECK() KP_HIP(hipGetLastError())
+
+// Run a C-ABI body, translating exceptions to status codes.
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        return KP_OK;
+    } catch (const Error& e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return KP_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return KP_ERR_HIP;
+    }
+}
+
+// ------------------------------------------------------------ device memory
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ FFT pass
+enum PreMode { PRE_NONE = 0, PRE_MAPS = 1, PRE_CHAN = 2 };
+enum PostMode { POST_NONE = 0, POST_MAPS = 1, POST_CHAN = 2 };
+enum Epi { EPI_STORE = 0, EPI_L2 = 1, EPI_Z = 2 };
+
+constexpr int kMaxStages = 12;
+
+struct FftPass {
+    const float2* in;
+    float2* out;
+    int64_t O, I;                  // outer count, inner (contiguous) count
+    int Lin, Lout, L;              // input rows, output rows, transform length
+    int64_t in_os, in_rs;          // element strides of input (outer, row); inner stride 1
+    int64_t out_os, out_rs;
+    int Ob, Ib;                    // columns per block: Ob outers x Ib inners
+    int nst;
+    int rad[kMaxStages];
+    const float2* tw;              // exp(-2 pi i m / L), m < L
+    int inverse;
+    int pad_in, crop_out;          // centred placement / centred crop
+    // fused pre-pass (first forward pass along the last image axis)
+    int pre;
+    const float2* px;              // image [O][Lin] (PRE_MAPS) or [O][Lin][I] (PRE_CHAN)
+    const float2* pmaps;           // [O][Lin][I] (PRE_MAPS)
+    const float* fo;               // per-outer factor [O]
+    const float* fr;               // per-row factor [Lin or Lout]
+    const float* xscale;           // optional device scalar multiplier
+    // fused post-pass (last adjoint pass along the last image axis)
+    int post;
+    float2* qx;                    // output image [O][Lout] (POST_MAPS) or channels
+    const float2* qmaps;
+    int epi;
+    float2* ex;                    // x (read, updated) for EPI_L2 / EPI_Z
+    float2* exbar;                 // xbar (written) for EPI_L2; z for EPI_Z
+    const float* e_tau;            // device scalars
+    const float* e_theta;
+    float e_lambda;
+};
+
+void launch_fft_pass(const FftPass& p, hipStream_t s);
+void fft_factor(int L, int* nst, int* rad);
+size_t fft_lds_bytes(int L, int ncol);
+
+// ------------------------------------------------------------ gridding
+struct KbParams {
+    float beta2_4;   // beta^2 / 4
+    float inv_half;  // 2 / W
+    float inv_w;     // 1 / W
+    int nterms;      // series terms of I0
+};
+
+enum InterpOut { IO_CALLER = 0, IO_INTERNAL = 1, IO_DUAL = 2, IO_PMUL = 3 };
+
+struct InterpArgs {
+    const float2* grid;       // [G][C]
+    const float* g;           // sorted grid coords [M][d]
+    const int32_t* perm;      // sorted -> caller
+    int64_t M;
+    int C;
+    int G[3];
+    int mode;
+    float2* out;              // caller [C][M] or internal [M][C]
+    // dual update / p multiply
+    float2* u;                // internal [M][C]
+    const float2* y;          // internal [M][C]
+    const float* p;           // internal [M][C] (MC) or [M] (SC) or null
+    int p_mc;
+    const float* sigma;       // device scalar
+};
+
+struct SpreadArgs {
+    float2* grid;             // [G][C]
+    const float* g;           // sorted coords [M][d]
+    const float2* k;          // internal k-space [M][C]
+    const int32_t* touch;     // entries (sorted sample positions)
+    const int4* work;         // (tile, start, count, atomic)
+    int64_t nwork;
+    int C;
+    int G[3];
+    int B[3];
+    int nb[3];
+};
+
+void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStream_t s);
+void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, int lds_bytes,
+                   hipStream_t s);
+void upload_kb_constants();
+
+// ------------------------------------------------------------ plan
+struct Plan {
+    int d = 0;
+    int64_t N[3] = {1, 1, 1};
+    int64_t Ntot = 0;
+    int64_t C = 1;
+    int64_t M = 0;
+    int G[3] = {1, 1, 1};
+    int64_t Gtot = 0;
+    int W = 4;
+    float alpha = 2.f;
+    double beta = 0;
+    KbParams kb{};
+    int B[3] = {1, 1, 1};
+    int nb[3] = {1, 1, 1};
+    int64_t nbins = 0;
+    int64_t ntouch = 0;
+    int64_t nwork = 0;
+    int64_t heavy_tiles = 0;
+    bool has_maps = false;
+    hipStream_t stream = nullptr;
+    int lds_max = 65536;
+    int spread_lds = 0;
+
+    DevBuf coords;                // caller's coordinates [M][d]
+    DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
+    DevBuf maps;                  // [N][C]
+    DevBuf fo_fwd, fr_fwd;        // deapodisation factors for the first/last pass
+    DevBuf tw[3];                 // twiddles per axis
+    DevBuf bufA, bufB;            // FFT ping-pong [>= Gtot*C]
+    DevBuf kint;                  // internal k-space [M][C]
+    DevBuf kint2;                 // second internal k-space (y for the solver)
+    DevBuf kint3;                 // third internal k-space (residuals, gradients)
+    DevBuf pint;                  // internal preconditioner [M][C]
+    DevBuf img[4];                // image workspaces [N]
+    DevBuf red;                   // reduction scratch
+    DevBuf sched;                 // schedule arrays
+    std::vector<int> fft_nst[3];
+    std::vector<int> fft_rad[3];
+    int64_t bytes = 0;
+};
+
+Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples,
+                  const float* coords, const void* maps, float oversamp, int kb_width,
+                  const kp_tuning* tuning, hipStream_t stream, bool channel_mode);
+void validate_plan_args(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples,
+                        const void* coords, const void* maps, float oversamp, int kb_width,
+                        const kp_tuning* tuning, bool channel_mode);
+
+// Operator drivers (internal layouts).  x/out images are [N] (maps) or
+// [N][C] (channel mode, no maps).
+struct FwdOpts {
+    const float* xscale = nullptr;   // device scalar multiplying x
+    bool channel = false;            // x is [N][C] (no maps)
+    int C = -1;                      // channels (<= plan C), -1 = plan C
+};
+// Pre-pass + FFT passes: image -> grid (result in plan bufA or bufB; returned)
+float2* forward_to_grid(Plan& P, const float2* x, const FwdOpts& o, hipStream_t s);
+// Spread internal k-space into grid (bufA)
+float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s);
+struct AdjOpts {
+    bool channel = false;
+    int C = -1;
+    int epi = EPI_STORE;
+    float2* ex = nullptr;
+    float2* exbar = nullptr;
+    const float* tau = nullptr;
+    const float* theta = nullptr;
+    float lambda = 0.f;
+};
+// Inverse FFT passes + post-pass from grid (in bufA) to image `out`
+void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStream_t s);
+
+void interp(Plan& P, const float2* grid, const InterpArgs& tmpl, hipStream_t s);
+
+// Elementwise helpers (solver.hip)
+void permute_to_internal(const float2* y_caller, float2* kint, const int32_t* perm, int64_t M,
+                         int C, hipStream_t s);
+void permute_to_caller(const float2* kint, float2* y_caller, const int32_t* perm, int64_t M,
+                       int C, hipStream_t s);
+void permute_p_to_internal(const float* p_caller, float* pint, const int32_t* perm, int64_t M,
+                           int C, bool mc, hipStream_t s);
+void permute_p_to_caller(const float* pint, float* p_caller, const int32_t* perm, int64_t M,
+                         int C, bool mc, hipStream_t s);
+
+int nterms_for(double beta2_4);
+
+// solver helpers (solver.hip)
+void fill2(float2* x, int64_t n, float re, float im, hipStream_t s);
+void copy2(const float2* a, float2* b, int64_t n, hipStream_t s);
+void reduce(const float2* a, const float2* b, int64_t n, int kind, double* out, double scale, bool accumulate,
+            double* part, hipStream_t s);
+void reduce_min(const float* p, int64_t n, float* out, float* part, hipStream_t s);
+void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s);
+void power_method(Plan& P, const float* pint, int p_mc, int iters, float* lam_out, hipStream_t s);
+const float* load_p(Plan& P, const float* p, int p_kind, hipStream_t s);
+void upload_wavelet_constants();
+void fft_twiddles(int L, DevBuf& tw);
+void pass_blocking(int64_t I, int* Ob, int* Ib);
+std::vector<double> db4_filter_host();
+
+}  // namespace kp
+
+struct kp_plan {
+    kp::Plan* impl;
+};

@@ -1,0 +1,942 @@
+// Plan construction: canonical grid coordinates, bit-exact stable bin sort,
+// tile touch lists, spreading work items, tables and workspaces; plus the
+// NUFFT forward / adjoint drivers and their C ABI.
+#include <cmath>
+#include <complex>
+#include <memory>
+#include <cstring>
+#include <mutex>
+#include <algorithm>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string t_last_error;
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+void DevBuf::alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        fail(KP_ERR_OOM, "hipMalloc(" + std::to_string(n) + ") failed: " + hipGetErrorString(e));
+    }
+    bytes = n;
+}
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+// ------------------------------------------------------------- scan (int32)
+constexpr int kScanBlock = 1024;
+
+__global__ void __launch_bounds__(256) k_scan_blocks(const int* in, int* out, int64_t n, int* bsum) {
+    __shared__ int sh[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + tid * 4;
+    int v[4], e[4], s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        e[i] = s;
+        s += v[i];
+    }
+    sh[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int t = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    const int pre = tid > 0 ? sh[tid - 1] : 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (base + i < n) out[base + i] = e[i] + pre;
+    if (tid == 255) bsum[blockIdx.x] = sh[255];
+}
+
+__global__ void k_add_offsets(int* out, int64_t n, const int* boff) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += boff[i / kScanBlock];
+}
+
+// exclusive scan of n ints (in may alias out)
+static void scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    DevBuf bsum, bscan;
+    bsum.alloc(sizeof(int) * (nb + 1));
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum.as<int>());
+    KP_LAUNCH_CHECK();
+    if (nb > 1) {
+        bscan.alloc(sizeof(int) * (nb + 1));
+        scan_exclusive(bsum.as<int>(), bscan.as<int>(), nb, s);
+        hipLaunchKernelGGL(k_add_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n,
+                           bscan.as<int>());
+        KP_LAUNCH_CHECK();
+    }
+    // keep the temporaries alive until the stream has used them
+    KP_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------- stable LSD radix sort
+constexpr int kRsThreads = 256, kRsItems = 8, kRsTile = kRsThreads * kRsItems;
+
+__global__ void __launch_bounds__(256) k_rs_hist(const uint32_t* keys, int64_t n, int shift, int* hist,
+                                                 int nblocks) {
+    __shared__ int h[16];
+    if (threadIdx.x < 16) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile + threadIdx.x * kRsItems;
+    for (int i = 0; i < kRsItems; ++i)
+        if (base + i < n) atomicAdd(&h[(keys[base + i] >> shift) & 15], 1);
+    __syncthreads();
+    if (threadIdx.x < 16) hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: thread t owns items [t*8, t*8+8) of the block's tile, so
+// the rank of an item among equal digits follows its index.
+__global__ void __launch_bounds__(256) k_rs_scatter(const uint32_t* kin, const int32_t* vin, uint32_t* kout,
+                                                    int32_t* vout, int64_t n, int shift,
+                                                    const int* hscan, int nblocks) {
+    __shared__ int cnt[16 * kRsThreads];
+    __shared__ int run[16 * kRsThreads];
+    __shared__ int tot[kRsThreads];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile + t * kRsItems;
+    for (int d = 0; d < 16; ++d) {
+        cnt[d * kRsThreads + t] = 0;
+        run[d * kRsThreads + t] = 0;
+    }
+    uint32_t k[kRsItems];
+    int32_t v[kRsItems];
+    for (int i = 0; i < kRsItems; ++i) {
+        if (base + i < n) {
+            k[i] = kin[base + i];
+            v[i] = vin[base + i];
+            cnt[((k[i] >> shift) & 15) * kRsThreads + t] += 1;
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the flattened [digit][thread] count table
+    int loc[16], s = 0;
+    for (int j = 0; j < 16; ++j) {
+        loc[j] = s;
+        s += cnt[t * 16 + j];
+    }
+    tot[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kRsThreads; off <<= 1) {
+        int x = t >= off ? tot[t - off] : 0;
+        __syncthreads();
+        tot[t] += x;
+        __syncthreads();
+    }
+    const int pre = t > 0 ? tot[t - 1] : 0;
+    __syncthreads();
+    for (int j = 0; j < 16; ++j) cnt[t * 16 + j] = loc[j] + pre;
+    __syncthreads();
+    for (int i = 0; i < kRsItems; ++i) {
+        if (base + i < n) {
+            const int d = (k[i] >> shift) & 15;
+            const int r = cnt[d * kRsThreads + t] - cnt[d * kRsThreads] + run[d * kRsThreads + t];
+            run[d * kRsThreads + t] += 1;
+            const int64_t pos = (int64_t)hscan[d * nblocks + blockIdx.x] + r;
+            kout[pos] = k[i];
+            vout[pos] = v[i];
+        }
+    }
+}
+
+// Sort (keys, vals) by key, stably; result in keys/vals.
+static void radix_sort_pairs(uint32_t* keys, int32_t* vals, int64_t n, uint32_t max_key, hipStream_t s) {
+    if (n <= 1) return;
+    int bits = 1;
+    while (bits < 32 && (max_key >> bits) != 0) ++bits;
+    const int passes = (bits + 3) / 4;
+    const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
+    DevBuf k2, v2, hist;
+    k2.alloc(sizeof(uint32_t) * n);
+    v2.alloc(sizeof(int32_t) * n);
+    hist.alloc(sizeof(int) * 16 * (int64_t)nblocks);
+    uint32_t *ka = keys, *kb = k2.as<uint32_t>();
+    int32_t *va = vals, *vb = v2.as<int32_t>();
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 4 * ps;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kRsThreads), 0, s, ka, n, shift, hist.as<int>(), nblocks);
+        KP_LAUNCH_CHECK();
+        scan_exclusive(hist.as<int>(), hist.as<int>(), 16 * (int64_t)nblocks, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift,
+                           hist.as<int>(), nblocks);
+        KP_LAUNCH_CHECK();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        KP_HIP(hipMemcpyAsync(keys, ka, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+        KP_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+    KP_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------ plan-time kernels
+struct Geom {
+    int d;
+    int G[3];
+    float Gf[3];
+    float half[3];
+    float c[3];   // fl32(G / (2 pi))
+    int B[3];
+    int nb[3];
+    int W;
+};
+
+// Canonical float32 grid coordinates; no contraction: every product and sum
+// is rounded separately (round to nearest even).
+__global__ void k_coords(const float* k, int64_t M, Geom gm, float* g, uint32_t* key, int* err) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    uint32_t kk = 0;
+    for (int ax = 0; ax < gm.d; ++ax) {
+        const float t = __fmul_rn(k[s * gm.d + ax], gm.c[ax]);
+        float ga = __fadd_rn(t, gm.half[ax]);
+        if (ga < 0.f) ga = __fadd_rn(ga, gm.Gf[ax]);
+        if (ga >= gm.Gf[ax]) ga = __fsub_rn(ga, gm.Gf[ax]);
+        if (!(ga >= 0.f && ga < gm.Gf[ax])) {
+            atomicOr(err, 1);
+            ga = 0.f;
+        }
+        g[s * gm.d + ax] = ga;
+        const int cell = (int)floorf(ga);
+        kk = kk * (uint32_t)gm.nb[ax] + (uint32_t)(cell / gm.B[ax]);
+    }
+    key[s] = kk;
+}
+
+__global__ void k_iota(int32_t* v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
+__global__ void k_count_keys(const uint32_t* key, int64_t n, int* cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[key[i]], 1);
+}
+
+__global__ void k_gather_coords(const float* g, const int32_t* perm, int64_t M, int d, float* gs) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    const int64_t i = perm[s];
+    for (int ax = 0; ax < d; ++ax) gs[s * d + ax] = g[i * d + ax];
+}
+
+// distinct tiles met by the W taps of a sample on one axis
+__device__ int axis_tiles(float g, const Geom& gm, int ax, int* tl) {
+    const int cell = (int)floorf(g);
+    int n = 0;
+    for (int t = 0; t < gm.W; ++t) {
+        int j = cell - gm.W / 2 + 1 + t;
+        j = j < 0 ? j + gm.G[ax] : (j >= gm.G[ax] ? j - gm.G[ax] : j);
+        const int tile = j / gm.B[ax];
+        bool seen = false;
+        for (int q = 0; q < n; ++q) seen |= (tl[q] == tile);
+        if (!seen) tl[n++] = tile;
+    }
+    return n;
+}
+
+__global__ void k_touch_count(const float* gs, int64_t M, Geom gm, int* cnt) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    int tl[8];
+    int prod = 1;
+    for (int ax = 0; ax < gm.d; ++ax) prod *= axis_tiles(gs[s * gm.d + ax], gm, ax, tl);
+    cnt[s] = prod;
+}
+
+__global__ void k_touch_emit(const float* gs, int64_t M, Geom gm, const int* off, uint32_t* keys,
+                             int32_t* vals) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    int tl[3][8], n[3] = {1, 1, 1};
+    for (int ax = 0; ax < gm.d; ++ax) n[ax] = axis_tiles(gs[s * gm.d + ax], gm, ax, tl[ax]);
+    for (int ax = gm.d; ax < 3; ++ax) tl[ax][0] = 0;
+    int pos = off[s];
+    for (int a = 0; a < n[0]; ++a)
+        for (int b = 0; b < n[1]; ++b)
+            for (int c = 0; c < n[2]; ++c) {
+                uint32_t key = (uint32_t)tl[0][a] * gm.nb[1] + tl[1][b];
+                if (gm.d == 3) key = key * gm.nb[2] + tl[2][c];
+                keys[pos] = key;
+                vals[pos] = (int32_t)s;
+                ++pos;
+            }
+}
+
+__global__ void k_maps_transpose(const float2* src, int64_t N, int C, float2* dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N * C) return;
+    const int64_t n = i / C;
+    const int c = (int)(i % C);
+    dst[i] = src[(int64_t)c * N + n];
+}
+
+__global__ void k_fill_c(float2* dst, int64_t n, float2 v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+__global__ void k_zero_tiles(float2* grid, const int* tiles, int ntiles, int d, Geom gm, int C) {
+    const int tile = tiles[blockIdx.x];
+    int tc[3] = {0, 0, 0};
+    int rem = tile;
+    for (int ax = d - 1; ax >= 0; --ax) {
+        tc[ax] = rem % gm.nb[ax];
+        rem /= gm.nb[ax];
+    }
+    const int Bt = gm.B[0] * gm.B[1] * (d == 3 ? gm.B[2] : 1);
+    for (int i = threadIdx.x; i < Bt * C; i += blockDim.x) {
+        const int l = i / C, c = i % C;
+        int64_t gidx;
+        if (d == 2) {
+            gidx = (int64_t)(tc[0] * gm.B[0] + l / gm.B[1]) * gm.G[1] + tc[1] * gm.B[1] + l % gm.B[1];
+        } else {
+            const int l2 = l % gm.B[2], l01 = l / gm.B[2];
+            gidx = ((int64_t)(tc[0] * gm.B[0] + l01 / gm.B[1]) * gm.G[1] + tc[1] * gm.B[1] + l01 % gm.B[1]) *
+                       gm.G[2] +
+                   tc[2] * gm.B[2] + l2;
+        }
+        grid[gidx * C + c] = make_float2(0.f, 0.f);
+    }
+}
+
+static unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// --------------------------------------------------------------- helpers
+static bool smooth5_even(int64_t g) {
+    if (g <= 0 || g % 2) return false;
+    for (int p : {2, 3, 5})
+        while (g % p == 0) g /= p;
+    return g == 1;
+}
+
+static int next_smooth_even(int64_t n) {
+    int64_t m = std::max<int64_t>(2, n);
+    while (!smooth5_even(m)) ++m;
+    return (int)m;
+}
+
+static double kb_ft_host(double nu, int W, double beta) {
+    const double z2 = beta * beta - (M_PI * W * nu) * (M_PI * W * nu);
+    if (z2 > 0) {
+        const double z = std::sqrt(z2);
+        return z == 0 ? 1.0 : std::sinh(z) / z;
+    }
+    const double z = std::sqrt(-z2);
+    return z == 0 ? 1.0 : std::sin(z) / z;
+}
+
+static Geom make_geom(const Plan& P) {
+    Geom gm{};
+    gm.d = P.d;
+    gm.W = P.W;
+    for (int a = 0; a < 3; ++a) {
+        gm.G[a] = P.G[a];
+        gm.Gf[a] = (float)P.G[a];
+        gm.half[a] = (float)(P.G[a] / 2);
+        gm.c[a] = (float)((double)P.G[a] / (2.0 * M_PI));
+        gm.B[a] = P.B[a];
+        gm.nb[a] = P.nb[a];
+    }
+    return gm;
+}
+
+void validate_plan_args(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples,
+                        const void* coords, const void* maps, float oversamp, int kb_width,
+                        const kp_tuning* tuning, bool channel_mode) {
+    if (ndim != 2 && ndim != 3) fail(KP_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    if (!shape) fail(KP_ERR_INVALID_ARG, "shape is NULL");
+    for (int a = 0; a < ndim; ++a) {
+        if (shape[a] < 2 || shape[a] > 4096) fail(KP_ERR_INVALID_ARG, "every N_a must lie in [2, 4096]");
+        if (shape[a] % 2) fail(KP_ERR_INVALID_ARG, "every N_a must be even");
+    }
+    if (ncoils < 1) fail(KP_ERR_INVALID_ARG, "ncoils must be >= 1");
+    if (ncoils > 16) fail(KP_ERR_UNSUPPORTED, "at most 16 coils are supported");
+    if (nsamples < 1) fail(KP_ERR_INVALID_ARG, "nsamples must be >= 1");
+    if (nsamples >= (int64_t)1 << 27) fail(KP_ERR_UNSUPPORTED, "nsamples must be < 2^27");
+    if (!coords) fail(KP_ERR_INVALID_ARG, "coords is NULL");
+    if (!maps && ncoils != 1 && !channel_mode) fail(KP_ERR_INVALID_ARG, "maps == NULL requires ncoils == 1");
+    if (!(oversamp >= 1.25f && oversamp <= 2.0f)) fail(KP_ERR_INVALID_ARG, "oversamp must lie in [1.25, 2]");
+    if (kb_width != 2 && kb_width != 4 && kb_width != 6 && kb_width != 8)
+        fail(KP_ERR_INVALID_ARG, "kb_width must be 2, 4, 6 or 8");
+    int64_t gtot = 1;
+    for (int a = 0; a < ndim; ++a) {
+        const int g = next_smooth_even((int64_t)std::ceil((double)oversamp * (double)shape[a]));
+        if (g < kb_width) fail(KP_ERR_UNSUPPORTED, "grid smaller than the kernel width");
+        gtot *= g;
+        if (tuning && tuning->bin_size[a] > 0 && g % tuning->bin_size[a] != 0)
+            fail(KP_ERR_INVALID_ARG, "tuning.bin_size must divide the grid size");
+    }
+    if (gtot * ncoils >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "grid x coils must be < 2^31 elements");
+    if (tuning && tuning->max_chunk < 0) fail(KP_ERR_INVALID_ARG, "tuning.max_chunk must be >= 0");
+}
+
+static int pick_bin(int G, int target) {
+    int best = 1;
+    for (int b = 1; b <= G; ++b)
+        if (G % b == 0 && b <= target) best = b;
+    return best;
+}
+
+static void set_lds_limit(const void* fn, int bytes) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipGetLastError();
+}
+
+Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples, const float* coords,
+                  const void* maps, float oversamp, int kb_width, const kp_tuning* tuning, hipStream_t s,
+                  bool channel_mode) {
+    validate_plan_args(ndim, shape, ncoils, nsamples, coords, maps, oversamp, kb_width, tuning, channel_mode);
+    upload_kb_constants();
+    auto P = std::make_unique<Plan>();
+    P->d = ndim;
+    P->C = ncoils;
+    P->M = nsamples;
+    P->W = kb_width;
+    P->alpha = oversamp;
+    P->stream = s;
+    P->Ntot = 1;
+    P->Gtot = 1;
+    for (int a = 0; a < ndim; ++a) {
+        P->N[a] = shape[a];
+        P->G[a] = next_smooth_even((int64_t)std::ceil((double)oversamp * (double)shape[a]));
+        P->Ntot *= P->N[a];
+        P->Gtot *= P->G[a];
+    }
+    const double a = (double)oversamp, w = (double)kb_width;
+    P->beta = M_PI * std::sqrt((w / a) * (w / a) * (a - 0.5) * (a - 0.5) - 0.8);
+    P->kb.beta2_4 = (float)(P->beta * P->beta / 4.0);
+    P->kb.inv_half = (float)(2.0 / w);
+    P->kb.inv_w = (float)(1.0 / w);
+    P->kb.nterms = nterms_for(P->beta * P->beta / 4.0);
+
+    int dev = 0;
+    KP_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    KP_HIP(hipGetDeviceProperties(&prop, dev));
+    P->lds_max = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+
+    // tiles: about 48 KB of LDS accumulator (C floats x 2 per cell)
+    const int C = (int)ncoils;
+    const double cells = 49152.0 / (8.0 * C);
+    const int target = (int)std::floor(std::pow(cells, 1.0 / ndim) + 1e-9);
+    for (int ax = 0; ax < 3; ++ax) {
+        if (ax >= ndim) {
+            P->B[ax] = 1;
+            P->nb[ax] = 1;
+            continue;
+        }
+        int b = (tuning && tuning->bin_size[ax] > 0) ? tuning->bin_size[ax] : pick_bin(P->G[ax], std::max(target, 1));
+        P->B[ax] = b;
+        P->nb[ax] = P->G[ax] / b;
+    }
+    P->nbins = (int64_t)P->nb[0] * P->nb[1] * P->nb[2];
+    P->spread_lds = (int)(8 * (int64_t)P->B[0] * P->B[1] * P->B[2] * C);
+    if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading tile does not fit in LDS");
+    if (P->nbins >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");
+    const int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 2048;
+
+    const int64_t M = nsamples;
+    const int d = ndim;
+    Geom gm = make_geom(*P);
+
+    // ---- canonical coordinates and bin keys
+    P->coords.alloc(sizeof(float) * M * d);
+    KP_HIP(hipMemcpyAsync(P->coords.p, coords, sizeof(float) * M * d, hipMemcpyDeviceToDevice, s));
+    P->g_orig.alloc(sizeof(float) * M * d);
+    DevBuf keys, err;
+    keys.alloc(sizeof(uint32_t) * M);
+    err.alloc(sizeof(int));
+    KP_HIP(hipMemsetAsync(err.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_coords, dim3(nblk(M)), dim3(256), 0, s, coords, M, gm, P->g_orig.as<float>(),
+                       keys.as<uint32_t>(), err.as<int>());
+    KP_LAUNCH_CHECK();
+    int herr = 0;
+    KP_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    KP_HIP(hipStreamSynchronize(s));
+    if (herr) fail(KP_ERR_INVALID_ARG, "coordinate out of range (|omega| beyond ~3 pi, NaN or inf)");
+
+    // ---- stable sort of samples by tile
+    P->perm.alloc(sizeof(int32_t) * M);
+    hipLaunchKernelGGL(k_iota, dim3(nblk(M)), dim3(256), 0, s, P->perm.as<int32_t>(), M);
+    KP_LAUNCH_CHECK();
+    radix_sort_pairs(keys.as<uint32_t>(), P->perm.as<int32_t>(), M, (uint32_t)(P->nbins - 1), s);
+    P->bin_off.alloc(sizeof(int) * (P->nbins + 1));
+    KP_HIP(hipMemsetAsync(P->bin_off.p, 0, sizeof(int) * (P->nbins + 1), s));
+    hipLaunchKernelGGL(k_count_keys, dim3(nblk(M)), dim3(256), 0, s, keys.as<uint32_t>(), M, P->bin_off.as<int>());
+    KP_LAUNCH_CHECK();
+    scan_exclusive(P->bin_off.as<int>(), P->bin_off.as<int>(), P->nbins + 1, s);
+    P->g_sorted.alloc(sizeof(float) * M * d);
+    hipLaunchKernelGGL(k_gather_coords, dim3(nblk(M)), dim3(256), 0, s, P->g_orig.as<float>(),
+                       P->perm.as<int32_t>(), M, d, P->g_sorted.as<float>());
+    KP_LAUNCH_CHECK();
+
+    // ---- tile touch lists
+    DevBuf tcnt;
+    tcnt.alloc(sizeof(int) * (M + 1));
+    KP_HIP(hipMemsetAsync(tcnt.p, 0, sizeof(int) * (M + 1), s));
+    hipLaunchKernelGGL(k_touch_count, dim3(nblk(M)), dim3(256), 0, s, P->g_sorted.as<float>(), M, gm,
+                       tcnt.as<int>());
+    KP_LAUNCH_CHECK();
+    scan_exclusive(tcnt.as<int>(), tcnt.as<int>(), M + 1, s);
+    int ntouch = 0;
+    KP_HIP(hipMemcpyAsync(&ntouch, tcnt.as<int>() + M, sizeof(int), hipMemcpyDeviceToHost, s));
+    KP_HIP(hipStreamSynchronize(s));
+    P->ntouch = ntouch;
+    DevBuf tkeys;
+    tkeys.alloc(sizeof(uint32_t) * std::max(ntouch, 1));
+    P->touch.alloc(sizeof(int32_t) * std::max(ntouch, 1));
+    hipLaunchKernelGGL(k_touch_emit, dim3(nblk(M)), dim3(256), 0, s, P->g_sorted.as<float>(), M, gm,
+                       tcnt.as<int>(), tkeys.as<uint32_t>(), P->touch.as<int32_t>());
+    KP_LAUNCH_CHECK();
+    radix_sort_pairs(tkeys.as<uint32_t>(), P->touch.as<int32_t>(), ntouch, (uint32_t)(P->nbins - 1), s);
+    P->touch_off.alloc(sizeof(int) * (P->nbins + 1));
+    KP_HIP(hipMemsetAsync(P->touch_off.p, 0, sizeof(int) * (P->nbins + 1), s));
+    hipLaunchKernelGGL(k_count_keys, dim3(nblk(ntouch)), dim3(256), 0, s, tkeys.as<uint32_t>(), (int64_t)ntouch,
+                       P->touch_off.as<int>());
+    KP_LAUNCH_CHECK();
+    scan_exclusive(P->touch_off.as<int>(), P->touch_off.as<int>(), P->nbins + 1, s);
+
+    // ---- spreading work items (host): heavy tiles split, largest work first
+    std::vector<int> toff(P->nbins + 1);
+    KP_HIP(hipMemcpyAsync(toff.data(), P->touch_off.p, sizeof(int) * (P->nbins + 1), hipMemcpyDeviceToHost, s));
+    KP_HIP(hipStreamSynchronize(s));
+    std::vector<int4> heavy_items, light_items;
+    std::vector<int> heavy;
+    for (int64_t t = 0; t < P->nbins; ++t) {
+        const int o = toff[t], n = toff[t + 1] - toff[t];
+        if (n <= max_chunk) {
+            light_items.push_back(make_int4((int)t, o, n, 0));
+        } else {
+            heavy.push_back((int)t);
+            for (int q = 0; q < n; q += max_chunk) heavy_items.push_back(make_int4((int)t, o + q, std::min(max_chunk, n - q), 1));
+        }
+    }
+    std::stable_sort(light_items.begin(), light_items.end(), [](const int4& x, const int4& y) { return x.z > y.z; });
+    std::vector<int4> items(heavy_items);
+    items.insert(items.end(), light_items.begin(), light_items.end());
+    P->nwork = (int64_t)items.size();
+    P->heavy_tiles = (int64_t)heavy.size();
+    P->work.alloc(sizeof(int4) * items.size());
+    KP_HIP(hipMemcpy(P->work.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice));
+    P->heavy_list.alloc(sizeof(int) * std::max<size_t>(heavy.size(), 1));
+    if (!heavy.empty())
+        KP_HIP(hipMemcpy(P->heavy_list.p, heavy.data(), sizeof(int) * heavy.size(), hipMemcpyHostToDevice));
+
+    // ---- coil maps, stored [N][C]; unit maps for a single coil without maps
+    P->has_maps = maps != nullptr;
+    P->maps.alloc(sizeof(float2) * P->Ntot * C);
+    if (maps && !channel_mode) {
+        hipLaunchKernelGGL(k_maps_transpose, dim3(nblk(P->Ntot * C)), dim3(256), 0, s, (const float2*)maps, P->Ntot,
+                           C, P->maps.as<float2>());
+    } else {
+        hipLaunchKernelGGL(k_fill_c, dim3(nblk(P->Ntot * C)), dim3(256), 0, s, P->maps.as<float2>(), P->Ntot * C,
+                           make_float2(1.f, 0.f));
+    }
+    KP_LAUNCH_CHECK();
+
+    // ---- deapodisation factors: f_a[m] = (-1)^n / Chat(n / G_a), n = m - N_a/2;
+    // 1/sqrt(N) folded into axis 0; fo = product over the leading axes
+    std::vector<std::vector<double>> f(d);
+    for (int ax = 0; ax < d; ++ax) {
+        f[ax].resize(P->N[ax]);
+        for (int64_t m = 0; m < P->N[ax]; ++m) {
+            const int64_t n = m - P->N[ax] / 2;
+            const double sign = (std::llabs(n) % 2) ? -1.0 : 1.0;
+            f[ax][m] = sign / kb_ft_host((double)n / P->G[ax], P->W, P->beta);
+        }
+    }
+    for (auto& v : f[0]) v /= std::sqrt((double)P->Ntot);
+    const int64_t O = P->Ntot / P->N[d - 1];
+    std::vector<float> fo(O), fr(P->N[d - 1]);
+    for (int64_t o = 0; o < O; ++o) {
+        if (d == 2) {
+            fo[o] = (float)f[0][o];
+        } else {
+            fo[o] = (float)(f[0][o / P->N[1]] * f[1][o % P->N[1]]);
+        }
+    }
+    for (int64_t m = 0; m < P->N[d - 1]; ++m) fr[m] = (float)f[d - 1][m];
+    P->fo_fwd.alloc(sizeof(float) * O);
+    P->fr_fwd.alloc(sizeof(float) * fr.size());
+    KP_HIP(hipMemcpy(P->fo_fwd.p, fo.data(), sizeof(float) * O, hipMemcpyHostToDevice));
+    KP_HIP(hipMemcpy(P->fr_fwd.p, fr.data(), sizeof(float) * fr.size(), hipMemcpyHostToDevice));
+
+    // ---- twiddles per axis
+    for (int ax = 0; ax < d; ++ax) {
+        const int L = P->G[ax];
+        fft_twiddles(L, P->tw[ax]);
+        int nst = 0, rad[kMaxStages];
+        fft_factor(L, &nst, rad);
+        P->fft_nst[ax].assign(1, nst);
+        P->fft_rad[ax].assign(rad, rad + nst);
+    }
+
+    // ---- workspaces
+    P->bufA.alloc(sizeof(float2) * P->Gtot * C);
+    P->bufB.alloc(sizeof(float2) * P->Gtot * C);
+    P->kint.alloc(sizeof(float2) * M * C);
+    P->kint2.alloc(sizeof(float2) * M * C);
+    P->kint3.alloc(sizeof(float2) * M * C);
+    P->pint.alloc(sizeof(float) * M * C);
+    for (auto& b : P->img) b.alloc(sizeof(float2) * P->Ntot * (channel_mode ? C : 1));
+    P->red.alloc(sizeof(double) * 65536);
+    P->sched.alloc(sizeof(float) * (3 * 8192 + 64));
+    KP_HIP(hipStreamSynchronize(s));
+
+    int64_t total = 0;
+    for (DevBuf* b : {&P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->touch_off, &P->touch, &P->work,
+                      &P->heavy_list, &P->maps, &P->fo_fwd, &P->fr_fwd, &P->bufA, &P->bufB, &P->kint, &P->kint2, &P->kint3,
+                      &P->pint, &P->red, &P->sched})
+        total += (int64_t)b->bytes;
+    for (auto& b : P->img) total += (int64_t)b.bytes;
+    for (auto& b : P->tw) total += (int64_t)b.bytes;
+    P->bytes = total;
+    return P.release();
+}
+
+// ------------------------------------------------------------ operators
+void fft_twiddles(int L, DevBuf& twb) {
+    std::vector<float2> tw(L);
+    for (int m = 0; m < L; ++m) {
+        const double ang = -2.0 * M_PI * (double)m / (double)L;
+        tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    twb.alloc(sizeof(float2) * L);
+    KP_HIP(hipMemcpy(twb.p, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice));
+}
+
+void pass_blocking(int64_t I, int* Ob, int* Ib) {
+    if (I >= 16) {
+        *Ib = 16;
+        *Ob = 1;
+    } else {
+        *Ib = (int)I;
+        *Ob = std::max<int>(1, 16 / (int)I);
+    }
+}
+
+static void fill_stages(const Plan& P, int ax, FftPass& fp) {
+    fp.nst = P.fft_nst[ax][0];
+    for (int i = 0; i < fp.nst; ++i) fp.rad[i] = P.fft_rad[ax][i];
+    fp.tw = P.tw[ax].as<float2>();
+}
+
+float2* forward_to_grid(Plan& P, const float2* x, const FwdOpts& o, hipStream_t s) {
+    const int C = o.C < 0 ? (int)P.C : o.C;
+    const int d = P.d;
+    float2* bufs[2] = {P.bufA.as<float2>(), P.bufB.as<float2>()};
+    int which = 0;
+    const float2* prev = nullptr;
+    for (int p = 0; p < d; ++p) {
+        const int ax = d - 1 - p;
+        FftPass fp{};
+        fp.L = P.G[ax];
+        fp.Lin = (int)P.N[ax];
+        fp.Lout = P.G[ax];
+        fp.pad_in = 1;
+        fp.crop_out = 0;
+        fp.inverse = 0;
+        int64_t O = 1, I = C;
+        for (int b = 0; b < ax; ++b) O *= P.N[b];
+        for (int b = ax + 1; b < d; ++b) I *= P.G[b];
+        fp.O = O;
+        fp.I = I;
+        fp.in_os = (int64_t)fp.Lin * I;
+        fp.in_rs = I;
+        fp.out_os = (int64_t)fp.Lout * I;
+        fp.out_rs = I;
+        fill_stages(P, ax, fp);
+        fp.out = bufs[which];
+        if (p == 0) {
+            fp.pre = o.channel ? PRE_CHAN : PRE_MAPS;
+            fp.px = x;
+            fp.pmaps = P.maps.as<float2>();
+            fp.fo = P.fo_fwd.as<float>();
+            fp.fr = P.fr_fwd.as<float>();
+            fp.xscale = o.xscale;
+        } else {
+            fp.pre = PRE_NONE;
+            fp.in = prev;
+        }
+        pass_blocking(I, &fp.Ob, &fp.Ib);
+        launch_fft_pass(fp, s);
+        prev = fp.out;
+        which ^= 1;
+    }
+    return const_cast<float2*>(prev);
+}
+
+void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStream_t s) {
+    const int C = o.C < 0 ? (int)P.C : o.C;
+    const int d = P.d;
+    const float2* cur = grid;
+    for (int ax = 0; ax < d; ++ax) {
+        float2* dst = (cur == P.bufA.as<float2>()) ? P.bufB.as<float2>() : P.bufA.as<float2>();
+        FftPass fp{};
+        fp.L = P.G[ax];
+        fp.Lin = P.G[ax];
+        fp.Lout = (int)P.N[ax];
+        fp.pad_in = 0;
+        fp.crop_out = 1;
+        fp.inverse = 1;
+        int64_t O = 1, I = C;
+        for (int b = 0; b < ax; ++b) O *= P.N[b];
+        for (int b = ax + 1; b < d; ++b) I *= P.G[b];
+        fp.O = O;
+        fp.I = I;
+        fp.in_os = (int64_t)fp.Lin * I;
+        fp.in_rs = I;
+        fp.out_os = (int64_t)fp.Lout * I;
+        fp.out_rs = I;
+        fill_stages(P, ax, fp);
+        fp.in = cur;
+        if (ax == d - 1) {
+            fp.post = o.channel ? POST_CHAN : POST_MAPS;
+            fp.qx = out;
+            fp.qmaps = P.maps.as<float2>();
+            fp.fo = P.fo_fwd.as<float>();
+            fp.fr = P.fr_fwd.as<float>();
+            fp.epi = o.epi;
+            fp.ex = o.ex;
+            fp.exbar = o.exbar;
+            fp.e_tau = o.tau;
+            fp.e_theta = o.theta;
+            fp.e_lambda = o.lambda;
+            if (!o.channel) {
+                fp.Ib = C;
+                fp.Ob = std::max(1, 16 / C);
+            } else {
+                pass_blocking(I, &fp.Ob, &fp.Ib);
+            }
+        } else {
+            fp.post = POST_NONE;
+            fp.out = dst;
+            pass_blocking(I, &fp.Ob, &fp.Ib);
+        }
+        launch_fft_pass(fp, s);
+        cur = dst;
+    }
+}
+
+float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
+    float2* grid = P.bufA.as<float2>();
+    Geom gm = make_geom(P);
+    if (P.heavy_tiles > 0) {
+        hipLaunchKernelGGL(k_zero_tiles, dim3((unsigned)P.heavy_tiles), dim3(256), 0, s, grid,
+                           P.heavy_list.as<int>(), (int)P.heavy_tiles, P.d, gm, C);
+        KP_LAUNCH_CHECK();
+    }
+    SpreadArgs a{};
+    a.grid = grid;
+    a.g = P.g_sorted.as<float>();
+    a.k = kint;
+    a.touch = P.touch.as<int32_t>();
+    a.work = P.work.as<int4>();
+    a.nwork = P.nwork;
+    a.C = C;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.G[ax] = P.G[ax];
+        a.B[ax] = P.B[ax];
+        a.nb[ax] = P.nb[ax];
+    }
+    const int lds = (int)(8 * (int64_t)P.B[0] * P.B[1] * P.B[2] * C);
+    launch_spread(P.d, P.W, a, P.kb, lds, s);
+    return grid;
+}
+
+void interp(Plan& P, const float2* grid, const InterpArgs& tmpl, hipStream_t s) {
+    InterpArgs a = tmpl;
+    a.grid = grid;
+    a.g = P.g_sorted.as<float>();
+    a.perm = P.perm.as<int32_t>();
+    a.M = P.M;
+    if (a.C <= 0) a.C = (int)P.C;
+    for (int ax = 0; ax < 3; ++ax) a.G[ax] = P.G[ax];
+    launch_interp(P.d, P.W, a, P.kb, s);
+}
+
+// ------------------------------------------------------------ db4 filter
+// Daubechies' construction: |m0|^2 = cos^8(xi/2) P(sin^2(xi/2)) with
+// P(y) = 1 + 4y + 10y^2 + 20y^3; minimum-phase spectral factor.
+std::vector<double> db4_filter_host() {
+    // roots of 20 y^3 + 10 y^2 + 4 y + 1 by Durand-Kerner iteration
+    typedef std::complex<double> cd;
+    const double c[4] = {1.0, 4.0, 10.0, 20.0};
+    auto poly = [&](cd y) { return ((c[3] * y + c[2]) * y + c[1]) * y + c[0]; };
+    cd r[3] = {cd(0.4, 0.9), cd(0.4, 0.9) * cd(0.4, 0.9), cd(0.4, 0.9) * cd(0.4, 0.9) * cd(0.4, 0.9)};
+    for (int it = 0; it < 500; ++it) {
+        for (int i = 0; i < 3; ++i) {
+            cd den = c[3];
+            for (int j = 0; j < 3; ++j)
+                if (j != i) den *= (r[i] - r[j]);
+            r[i] -= poly(r[i]) / den;
+        }
+    }
+    // z + 1/z = 2 - 4y; keep |z| < 1
+    std::vector<cd> pz = {cd(1.0)};
+    auto mul = [&](cd a0, cd a1) {  // multiply by (a0 + a1 z^-1)
+        std::vector<cd> q(pz.size() + 1, cd(0.0));
+        for (size_t i = 0; i < pz.size(); ++i) {
+            q[i] += pz[i] * a0;
+            q[i + 1] += pz[i] * a1;
+        }
+        pz = q;
+    };
+    for (int i = 0; i < 4; ++i) mul(1.0, 1.0);
+    for (int i = 0; i < 3; ++i) {
+        const cd b = 2.0 - 4.0 * r[i];
+        const cd disc = std::sqrt(b * b - 4.0);
+        cd z = (b + disc) / 2.0;
+        if (std::abs(z) >= 1.0) z = (b - disc) / 2.0;
+        mul(1.0, -z);
+    }
+    std::vector<double> h(8);
+    double sum = 0;
+    for (int i = 0; i < 8; ++i) {
+        h[i] = pz[i].real();
+        sum += h[i];
+    }
+    for (auto& v : h) v *= std::sqrt(2.0) / sum;
+    return h;
+}
+
+}  // namespace kp
+
+// ================================================================== C ABI
+using namespace kp;
+
+extern "C" {
+
+const char* kp_last_error(void) { return kp::t_last_error.c_str(); }
+
+int nufft_plan_validate(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples, const void* coords,
+                        const void* maps, float oversamp, int kb_width, const kp_tuning* tuning) {
+    return guarded([&] { validate_plan_args(ndim, shape, ncoils, nsamples, coords, maps, oversamp, kb_width, tuning, false); });
+}
+
+int nufft_plan(kp_plan_t* out, int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples, const float* coords,
+               const void* maps, float oversamp, int kb_width, const kp_tuning* tuning, void* stream) {
+    return guarded([&] {
+        if (!out) fail(KP_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        Plan* P = create_plan(ndim, shape, ncoils, nsamples, coords, maps, oversamp, kb_width, tuning,
+                              (hipStream_t)stream, false);
+        *out = new kp_plan{P};
+    });
+}
+
+void nufft_destroy(kp_plan_t plan) {
+    if (!plan) return;
+    if (plan->impl) {
+        (void)hipStreamSynchronize(plan->impl->stream);
+        (void)hipDeviceSynchronize();
+        delete plan->impl;
+    }
+    delete plan;
+}
+
+int nufft_forward(kp_plan_t plan, const void* x, void* y, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
+        if (!x || !y) fail(KP_ERR_INVALID_ARG, "x or y is NULL");
+        Plan& P = *plan->impl;
+        hipStream_t s = (hipStream_t)stream;
+        P.stream = s;
+        FwdOpts fo;
+        float2* grid = forward_to_grid(P, (const float2*)x, fo, s);
+        InterpArgs ia{};
+        ia.mode = IO_CALLER;
+        ia.out = (float2*)y;
+        interp(P, grid, ia, s);
+    });
+}
+
+int nufft_adjoint(kp_plan_t plan, const void* y, void* x, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
+        if (!x || !y) fail(KP_ERR_INVALID_ARG, "x or y is NULL");
+        Plan& P = *plan->impl;
+        hipStream_t s = (hipStream_t)stream;
+        P.stream = s;
+        permute_to_internal((const float2*)y, P.kint.as<float2>(), P.perm.as<int32_t>(), P.M, (int)P.C, s);
+        float2* grid = spread_to_grid(P, P.kint.as<float2>(), (int)P.C, s);
+        AdjOpts ao;
+        grid_to_image(P, grid, (float2*)x, ao, s);
+    });
+}
+
+int nufft_plan_info(kp_plan_t plan, kp_plan_info* info) {
+    return guarded([&] {
+        if (!plan || !plan->impl || !info) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        const Plan& P = *plan->impl;
+        std::memset(info, 0, sizeof(*info));
+        info->ndim = P.d;
+        for (int a = 0; a < 3; ++a) {
+            info->shape[a] = a < P.d ? P.N[a] : 1;
+            info->grid[a] = a < P.d ? P.G[a] : 1;
+            info->bin_size[a] = P.B[a];
+        }
+        info->ncoils = P.C;
+        info->nsamples = P.M;
+        info->kb_width = P.W;
+        info->oversamp = P.alpha;
+        info->kb_beta = P.beta;
+        info->nbins = P.nbins;
+        info->ntouch = P.ntouch;
+        info->nwork = P.nwork;
+        info->heavy_tiles = P.heavy_tiles;
+        info->workspace_bytes = P.bytes;
+    });
+}
+
+int nufft_plan_sort(kp_plan_t plan, int32_t* perm, int32_t* bin_offsets, int32_t* touch_offsets, int32_t* touch,
+                    void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
+        Plan& P = *plan->impl;
+        hipStream_t s = (hipStream_t)stream;
+        if (perm) KP_HIP(hipMemcpyAsync(perm, P.perm.p, sizeof(int32_t) * P.M, hipMemcpyDeviceToDevice, s));
+        if (bin_offsets)
+            KP_HIP(hipMemcpyAsync(bin_offsets, P.bin_off.p, sizeof(int32_t) * (P.nbins + 1), hipMemcpyDeviceToDevice, s));
+        if (touch_offsets)
+            KP_HIP(hipMemcpyAsync(touch_offsets, P.touch_off.p, sizeof(int32_t) * (P.nbins + 1), hipMemcpyDeviceToDevice, s));
+        if (touch && P.ntouch > 0)
+            KP_HIP(hipMemcpyAsync(touch, P.touch.p, sizeof(int32_t) * P.ntouch, hipMemcpyDeviceToDevice, s));
+    });
+}
+
+int nufft_plan_grid_coords(kp_plan_t plan, float* g, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl || !g) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        Plan& P = *plan->impl;
+        KP_HIP(hipMemcpyAsync(g, P.g_orig.p, sizeof(float) * P.M * P.d, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    });
+}
+
+int kp_db4_filter(double* h8) {
+    return guarded([&] {
+        if (!h8) fail(KP_ERR_INVALID_ARG, "h8 is NULL");
+        auto h = db4_filter_host();
+        for (int i = 0; i < 8; ++i) h8[i] = h[i];
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,581 @@
+// PDHG solver: layout permutes, deterministic reductions, power method,
+// step-size schedule, periodised db4 wavelet prox, the solve loop and its
+// C ABI.
+#include <cmath>
+#include <cstring>
+#include <algorithm>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+static unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------- permutes
+__global__ void k_perm_in(const float2* y, float2* k, const int32_t* perm, int64_t M, int C) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * C) return;
+    const int64_t s = i / C;
+    const int c = (int)(i % C);
+    k[i] = y[(int64_t)c * M + perm[s]];
+}
+__global__ void k_perm_out(const float2* k, float2* y, const int32_t* perm, int64_t M, int C) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * C) return;
+    const int64_t s = i / C;
+    const int c = (int)(i % C);
+    y[(int64_t)c * M + perm[s]] = k[i];
+}
+__global__ void k_perm_p_in(const float* p, float* q, const int32_t* perm, int64_t M, int C, int mc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (mc) {
+        if (i >= M * C) return;
+        const int64_t s = i / C;
+        const int c = (int)(i % C);
+        q[i] = p[(int64_t)c * M + perm[s]];
+    } else {
+        if (i >= M) return;
+        q[i] = p[perm[i]];
+    }
+}
+__global__ void k_perm_p_out(const float* q, float* p, const int32_t* perm, int64_t M, int C, int mc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (mc) {
+        if (i >= M * C) return;
+        const int64_t s = i / C;
+        const int c = (int)(i % C);
+        p[(int64_t)c * M + perm[s]] = q[i];
+    } else {
+        if (i >= M) return;
+        p[perm[i]] = q[i];
+    }
+}
+
+void permute_to_internal(const float2* y, float2* k, const int32_t* perm, int64_t M, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_in, dim3(nblk(M * C)), dim3(256), 0, s, y, k, perm, M, C);
+    KP_LAUNCH_CHECK();
+}
+void permute_to_caller(const float2* k, float2* y, const int32_t* perm, int64_t M, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_out, dim3(nblk(M * C)), dim3(256), 0, s, k, y, perm, M, C);
+    KP_LAUNCH_CHECK();
+}
+void permute_p_to_internal(const float* p, float* q, const int32_t* perm, int64_t M, int C, bool mc, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_p_in, dim3(nblk(M * (mc ? C : 1))), dim3(256), 0, s, p, q, perm, M, C, (int)mc);
+    KP_LAUNCH_CHECK();
+}
+void permute_p_to_caller(const float* q, float* p, const int32_t* perm, int64_t M, int C, bool mc, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_p_out, dim3(nblk(M * (mc ? C : 1))), dim3(256), 0, s, q, p, perm, M, C, (int)mc);
+    KP_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------- elementwise
+__global__ void k_fill2(float2* x, int64_t n, float2 v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+__global__ void k_copy2(const float2* a, float2* b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+void fill2(float2* x, int64_t n, float re, float im, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill2, dim3(nblk(n)), dim3(256), 0, s, x, n, make_float2(re, im));
+    KP_LAUNCH_CHECK();
+}
+void copy2(const float2* a, float2* b, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy2, dim3(nblk(n)), dim3(256), 0, s, a, b, n);
+    KP_LAUNCH_CHECK();
+}
+
+// x_new = z (prox result), xbar = x_new + theta (x_new - x), x = x_new
+__global__ void k_extrapolate(const float2* xn, float2* x, float2* xbar, int64_t n, const float* theta) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float th = *theta;
+    const float2 a = xn[i], b = x[i];
+    xbar[i] = make_float2(a.x + th * (a.x - b.x), a.y + th * (a.y - b.y));
+    x[i] = a;
+}
+
+// complex soft threshold v max(1 - t/|v|, 0) with t = scale * (*tau)
+__global__ void k_soft(float2* v, int64_t n, const float* tau, float lam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float t = *tau * lam;
+    const float2 a = v[i];
+    const float m = sqrtf(a.x * a.x + a.y * a.y);
+    const float f = m > t ? 1.f - t / m : 0.f;
+    v[i] = make_float2(a.x * f, a.y * f);
+}
+
+// ------------------------------------------------------------- reductions
+// Deterministic two-stage reductions: a fixed grid of partials, then one
+// block sums them in a fixed order.
+constexpr int kRedBlocks = 1024;
+
+__device__ double block_sum(double v) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ float block_min(float v) {
+    __shared__ float sm[256];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sm[threadIdx.x] = fminf(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    float r = sm[0];
+    __syncthreads();
+    return r;
+}
+
+// kinds: 0 = sum |a|^2, 1 = sum |a - b|^2, 2 = sum |a|, 3 = Re sum conj(a) b
+__global__ void k_red_partial(const float2* a, const float2* b, int64_t n, int kind, double* part) {
+    double acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 x = a[i];
+        if (kind == 0) {
+            acc += (double)x.x * x.x + (double)x.y * x.y;
+        } else if (kind == 1) {
+            const double dx = (double)x.x - b[i].x, dy = (double)x.y - b[i].y;
+            acc += dx * dx + dy * dy;
+        } else if (kind == 2) {
+            acc += sqrt((double)x.x * x.x + (double)x.y * x.y);
+        } else {
+            const float2 y = b[i];
+            acc += (double)x.x * y.x + (double)x.y * y.y;
+        }
+    }
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+__global__ void k_red_final(const double* part, int n, double* out, double scale, int accumulate) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0) *out = (accumulate ? *out : 0.0) + scale * r;
+}
+__global__ void k_min_partial(const float* p, int64_t n, float* part) {
+    float acc = INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc = fminf(acc, p[i]);
+    const float r = block_min(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+__global__ void k_min_final(const float* part, int n, float* out) {
+    float acc = INFINITY;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc = fminf(acc, part[i]);
+    const float r = block_min(acc);
+    if (threadIdx.x == 0) *out = r;
+}
+
+void reduce(const float2* a, const float2* b, int64_t n, int kind, double* out, double scale, bool accumulate,
+            double* part, hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_red_partial, dim3(nb), dim3(256), 0, s, a, b, n, kind, part);
+    KP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, part, nb, out, scale, (int)accumulate);
+    KP_LAUNCH_CHECK();
+}
+void reduce_min(const float* p, int64_t n, float* out, float* part, hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_min_partial, dim3(nb), dim3(256), 0, s, p, n, part);
+    KP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, part, nb, out);
+    KP_LAUNCH_CHECK();
+}
+
+// lam = sqrt(nrm2); scale = 1/lam (power method bookkeeping)
+__global__ void k_power_update(const double* nrm2, float* lam, float* scale) {
+    const double l = sqrt(*nrm2);
+    *lam = (float)l;
+    *scale = (float)(l > 0 ? 1.0 / l : 0.0);
+}
+
+// sigma_k, tau_k, theta_k for k < K (computed in double)
+__global__ void k_schedule(const float* lmax, const float* pmin, int K, float sigma0, int accel, float* sig,
+                           float* tau, float* th) {
+    double s = sigma0, t = 1.0 / ((double)sigma0 * (double)*lmax);
+    const double pm = *pmin;
+    for (int k = 0; k < K; ++k) {
+        const double h = accel ? 1.0 / (1.0 + 2.0 * s * pm) : 1.0;
+        sig[k] = (float)s;
+        tau[k] = (float)t;
+        th[k] = (float)h;
+        s = h * s;
+        t = t / h;
+    }
+}
+
+__global__ void k_set_scalar(float* p, float v) { *p = v; }
+
+// ------------------------------------------------------------- wavelet
+__constant__ float c_h[8];
+__constant__ float c_g[8];
+
+void upload_wavelet_constants() {
+    static bool done = false;
+    if (done) return;
+    auto h = db4_filter_host();
+    float hf[8], gf[8];
+    for (int t = 0; t < 8; ++t) {
+        hf[t] = (float)h[t];
+        gf[t] = (float)(((t % 2) ? -1.0 : 1.0) * h[7 - t]);
+    }
+    KP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_h), hf, sizeof(hf)));
+    KP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_g), gf, sizeof(gf)));
+    done = true;
+}
+
+struct DwtArgs {
+    float2* x;
+    int64_t S[3];      // element strides of the full image
+    int n[3];          // extents of the current approximation block
+    int d;
+    int ax;
+    int inverse;
+    int64_t O, I;      // outer / inner counts of the [O][L][I] view
+    int Ob, Ib;
+};
+
+__device__ __forceinline__ int64_t dwt_addr(const DwtArgs& a, int64_t o, int r, int64_t i) {
+    // o enumerates axes < ax, i enumerates axes > ax (C order within each)
+    int64_t off = 0;
+    int64_t rem = o;
+    for (int b = a.ax - 1; b >= 0; --b) {
+        off += (rem % a.n[b]) * a.S[b];
+        rem /= a.n[b];
+    }
+    rem = i;
+    for (int b = a.d - 1; b > a.ax; --b) {
+        off += (rem % a.n[b]) * a.S[b];
+        rem /= a.n[b];
+    }
+    return off + (int64_t)r * a.S[a.ax];
+}
+
+// One level along one axis of the approximation block, in place, through LDS.
+// analysis: a[k] = sum_t h[t] x[(2k+t) mod L], d[k] = sum_t g[t] x[(2k+t) mod L]
+// synthesis: its transpose.
+__global__ void __launch_bounds__(256) k_dwt_axis(DwtArgs a) {
+    extern __shared__ float2 buf[];
+    const int L = a.n[a.ax];
+    const int ncol = a.Ob * a.Ib;
+    const int64_t nIb = (a.I + a.Ib - 1) / a.Ib;
+    const int64_t o0 = (blockIdx.x / nIb) * a.Ob;
+    const int64_t i0 = (blockIdx.x % nIb) * a.Ib;
+    const bool last = (a.ax == a.d - 1);
+    // load: for the contiguous axis put rows fastest, otherwise columns
+    for (int idx = threadIdx.x; idx < L * ncol; idx += blockDim.x) {
+        int r, col;
+        if (last) {
+            r = idx % L;
+            col = idx / L;
+        } else {
+            r = idx / ncol;
+            col = idx % ncol;
+        }
+        const int64_t o = o0 + col / a.Ib, i = i0 + col % a.Ib;
+        float2 v = make_float2(0.f, 0.f);
+        if (o < a.O && i < a.I) v = a.x[dwt_addr(a, o, r, i)];
+        buf[r * ncol + col] = v;
+    }
+    __syncthreads();
+    const int h2 = L / 2;
+    float2 outv[2];
+    // compute into registers, then barrier, then write back in place (global)
+    for (int idx = threadIdx.x; idx < L * ncol; idx += blockDim.x) {
+        int r, col;
+        if (last) {
+            r = idx % L;
+            col = idx / L;
+        } else {
+            r = idx / ncol;
+            col = idx % ncol;
+        }
+        const int64_t o = o0 + col / a.Ib, i = i0 + col % a.Ib;
+        float2 acc = make_float2(0.f, 0.f);
+        if (!a.inverse) {
+            const int k = r < h2 ? r : r - h2;
+            const float* f = r < h2 ? c_h : c_g;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int src = (2 * k + t) % L;
+                const float2 v = buf[src * ncol + col];
+                acc.x += f[t] * v.x;
+                acc.y += f[t] * v.y;
+            }
+        } else {
+            // x[n] = sum_k h[n-2k] a[k] + g[n-2k] d[k], n-2k taken mod L in [0, 8)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = (r & 1) + 2 * q;
+                int k = (r - t) / 2;  // r - t is even
+                k = ((k % h2) + h2) % h2;
+                const float2 va = buf[k * ncol + col];
+                const float2 vd = buf[(h2 + k) * ncol + col];
+                acc.x += c_h[t] * va.x + c_g[t] * vd.x;
+                acc.y += c_h[t] * va.y + c_g[t] * vd.y;
+            }
+        }
+        if (o < a.O && i < a.I) a.x[dwt_addr(a, o, r, i)] = acc;
+    }
+    (void)outv;
+}
+
+void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s) {
+    int64_t S[3] = {1, 1, 1};
+    for (int b = d - 2; b >= 0; --b) S[b] = S[b + 1] * N[b + 1];
+    auto run_level = [&](int lev) {
+        int n[3] = {1, 1, 1};
+        for (int b = 0; b < d; ++b) n[b] = (int)(N[b] >> lev);
+        auto run_axis = [&](int ax) {
+            DwtArgs a{};
+            a.x = x;
+            for (int b = 0; b < 3; ++b) {
+                a.S[b] = S[b];
+                a.n[b] = n[b];
+            }
+            a.d = d;
+            a.ax = ax;
+            a.inverse = inverse ? 1 : 0;
+            a.O = 1;
+            a.I = 1;
+            for (int b = 0; b < ax; ++b) a.O *= n[b];
+            for (int b = ax + 1; b < d; ++b) a.I *= n[b];
+            const int L = n[ax];
+            if (ax == d - 1) {
+                a.Ib = 1;
+                a.Ob = std::max(1, std::min<int>(64, 4096 / L));
+            } else {
+                a.Ib = (int)std::min<int64_t>(a.I, 16);
+                a.Ob = 1;
+            }
+            const int ncol = a.Ob * a.Ib;
+            const int64_t nb = ((a.O + a.Ob - 1) / a.Ob) * ((a.I + a.Ib - 1) / a.Ib);
+            hipLaunchKernelGGL(k_dwt_axis, dim3((unsigned)nb), dim3(256), sizeof(float2) * L * ncol, s, a);
+            KP_LAUNCH_CHECK();
+        };
+        if (!inverse)
+            for (int ax = 0; ax < d; ++ax) run_axis(ax);
+        else
+            for (int ax = d - 1; ax >= 0; --ax) run_axis(ax);
+    };
+    if (!inverse)
+        for (int l = 0; l < levels; ++l) run_level(l);
+    else
+        for (int l = levels - 1; l >= 0; --l) run_level(l);
+}
+
+// ------------------------------------------------------------- operators
+// Apply A^H P A to v (power method step), result into `out`.
+static void normal_op(Plan& P, const float2* v, const float* xscale, const float* pint, int p_mc, float2* out,
+                      hipStream_t s) {
+    FwdOpts fo;
+    fo.xscale = xscale;
+    float2* grid = forward_to_grid(P, v, fo, s);
+    InterpArgs ia{};
+    ia.mode = IO_PMUL;
+    ia.out = P.kint3.as<float2>();
+    ia.p = pint;
+    ia.p_mc = p_mc;
+    interp(P, grid, ia, s);
+    float2* g2 = spread_to_grid(P, P.kint3.as<float2>(), (int)P.C, s);
+    AdjOpts ao;
+    grid_to_image(P, g2, out, ao, s);
+}
+
+// scalar slots in P.sched after the 3*8192 schedule entries
+enum { SL_LMAX = 0, SL_PMIN = 1, SL_SCALE = 2, SL_ONE = 3 };
+static float* slot(Plan& P, int i) { return P.sched.as<float>() + 3 * 8192 + i; }
+
+void power_method(Plan& P, const float* pint, int p_mc, int iters, float* lam_out, hipStream_t s) {
+    float2* v = P.img[2].as<float2>();
+    double* nrm = P.red.as<double>();
+    double* part = P.red.as<double>() + 16;
+    fill2(v, P.Ntot, (float)(1.0 / std::sqrt((double)P.Ntot)), 0.f, s);
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, slot(P, SL_SCALE), 1.f);
+    KP_LAUNCH_CHECK();
+    for (int it = 0; it < iters; ++it) {
+        normal_op(P, v, slot(P, SL_SCALE), pint, p_mc, v, s);
+        reduce(v, nullptr, P.Ntot, 0, nrm, 1.0, false, part, s);
+        hipLaunchKernelGGL(k_power_update, dim3(1), dim3(1), 0, s, nrm, lam_out, slot(P, SL_SCALE));
+        KP_LAUNCH_CHECK();
+    }
+}
+
+// objective 1/2 ||A x - y||^2 + g(x) into host
+static double objective(Plan& P, const float2* x, const float2* yint, int reg, float lam, int levels,
+                        hipStream_t s) {
+    double* acc = P.red.as<double>() + 8;
+    double* part = P.red.as<double>() + 16;
+    FwdOpts fo;
+    float2* grid = forward_to_grid(P, x, fo, s);
+    InterpArgs ia{};
+    ia.mode = IO_INTERNAL;
+    ia.out = P.kint3.as<float2>();
+    interp(P, grid, ia, s);
+    reduce(P.kint3.as<float2>(), yint, P.M * P.C, 1, acc, 0.5, false, part, s);
+    if (reg == KP_REG_L2) {
+        reduce(x, nullptr, P.Ntot, 0, acc, 0.5 * lam, true, part, s);
+    } else {
+        float2* w = P.img[3].as<float2>();
+        copy2(x, w, P.Ntot, s);
+        dwt(w, P.N, P.d, levels, false, s);
+        reduce(w, nullptr, P.Ntot, 2, acc, lam, true, part, s);
+    }
+    double h = 0;
+    KP_HIP(hipMemcpyAsync(&h, acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    KP_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+static void check_p(const Plan& P, const float* p, int p_kind) {
+    if (p_kind != KP_PRECOND_NONE && p_kind != KP_PRECOND_SC && p_kind != KP_PRECOND_MC)
+        fail(KP_ERR_INVALID_ARG, "p_kind must be NONE, SC or MC");
+    if (p_kind != KP_PRECOND_NONE && !p) fail(KP_ERR_INVALID_ARG, "p is NULL");
+    (void)P;
+}
+
+// load p into P.pint (internal order); returns the pointer to pass to kernels
+const float* load_p(Plan& P, const float* p, int p_kind, hipStream_t s) {
+    if (p_kind == KP_PRECOND_NONE) return nullptr;
+    const bool mc = p_kind == KP_PRECOND_MC;
+    permute_p_to_internal(p, P.pint.as<float>(), P.perm.as<int32_t>(), P.M, (int)P.C, mc, s);
+    return P.pint.as<float>();
+}
+
+void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, float2* x_out,
+                     float2* u_out, hipStream_t s) {
+    check_p(P, p, p_kind);
+    if (op.iters < 1 || op.iters > 8192) fail(KP_ERR_INVALID_ARG, "iters must lie in [1, 8192]");
+    if (op.reg != KP_REG_L2 && op.reg != KP_REG_L1_WAVELET) fail(KP_ERR_INVALID_ARG, "unknown regulariser");
+    if (!(op.lambda >= 0.f)) fail(KP_ERR_INVALID_ARG, "lambda must be >= 0");
+    if (!(op.sigma0 > 0.f)) fail(KP_ERR_INVALID_ARG, "sigma0 must be > 0");
+    const int levels = op.wavelet_levels;
+    if (op.reg == KP_REG_L1_WAVELET) {
+        if (levels < 1 || levels > 8) fail(KP_ERR_INVALID_ARG, "wavelet_levels must lie in [1, 8]");
+        for (int a = 0; a < P.d; ++a)
+            if (P.N[a] % (1 << levels)) fail(KP_ERR_INVALID_ARG, "every N_a must be divisible by 2^levels");
+        upload_wavelet_constants();
+    }
+    if (op.lambda_max <= 0.f && op.power_iters < 1) fail(KP_ERR_INVALID_ARG, "power_iters must be >= 1");
+    const int C = (int)P.C;
+    const int K = op.iters;
+    const int p_mc = p_kind == KP_PRECOND_MC ? 1 : 0;
+    float* sig = P.sched.as<float>();
+    float* tau = sig + 8192;
+    float* th = tau + 8192;
+
+    // y, p, u, x into internal layouts
+    float2* yint = P.kint2.as<float2>();
+    float2* u = P.kint.as<float2>();
+    permute_to_internal(y, yint, P.perm.as<int32_t>(), P.M, C, s);
+    const float* pint = load_p(P, p, p_kind, s);
+    if (op.u0)
+        permute_to_internal((const float2*)op.u0, u, P.perm.as<int32_t>(), P.M, C, s);
+    else
+        fill2(u, P.M * C, 0.f, 0.f, s);
+    float2* x = P.img[0].as<float2>();
+    float2* xbar = P.img[1].as<float2>();
+    float2* z = P.img[2].as<float2>();
+    if (op.x0)
+        copy2((const float2*)op.x0, x, P.Ntot, s);
+    else
+        fill2(x, P.Ntot, 0.f, 0.f, s);
+    copy2(x, xbar, P.Ntot, s);
+
+    // min p and lambda_max, then the schedule, all on the device
+    if (pint)
+        reduce_min(pint, P.M * (p_mc ? C : 1), slot(P, SL_PMIN), (float*)(P.red.as<double>() + 4096), s);
+    else
+        hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, slot(P, SL_PMIN), 1.f);
+    if (op.lambda_max > 0.f) {
+        hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), op.lambda_max);
+    } else {
+        power_method(P, pint, p_mc, op.power_iters, slot(P, SL_LMAX), s);
+    }
+    KP_LAUNCH_CHECK();
+    if (op.lambda_max_out)
+        KP_HIP(hipMemcpyAsync(op.lambda_max_out, slot(P, SL_LMAX), sizeof(float), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), slot(P, SL_PMIN), K, op.sigma0,
+                       op.accel, sig, tau, th);
+    KP_LAUNCH_CHECK();
+
+    if (op.objective_host) op.objective_host[0] = objective(P, x, yint, op.reg, op.lambda, levels, s);
+    for (int k = 0; k < K; ++k) {
+        FwdOpts fo;
+        float2* grid = forward_to_grid(P, xbar, fo, s);
+        InterpArgs ia{};
+        ia.mode = IO_DUAL;
+        ia.u = u;
+        ia.y = yint;
+        ia.p = pint;
+        ia.p_mc = p_mc;
+        ia.sigma = sig + k;
+        interp(P, grid, ia, s);
+        float2* g2 = spread_to_grid(P, u, C, s);
+        AdjOpts ao;
+        ao.ex = x;
+        ao.tau = tau + k;
+        ao.theta = th + k;
+        ao.lambda = op.lambda;
+        if (op.reg == KP_REG_L2) {
+            ao.epi = EPI_L2;
+            ao.exbar = xbar;
+            grid_to_image(P, g2, z, ao, s);
+        } else {
+            ao.epi = EPI_Z;
+            ao.exbar = z;
+            grid_to_image(P, g2, z, ao, s);
+            dwt(z, P.N, P.d, levels, false, s);
+            hipLaunchKernelGGL(k_soft, dim3(nblk(P.Ntot)), dim3(256), 0, s, z, P.Ntot, tau + k, op.lambda);
+            KP_LAUNCH_CHECK();
+            dwt(z, P.N, P.d, levels, true, s);
+            hipLaunchKernelGGL(k_extrapolate, dim3(nblk(P.Ntot)), dim3(256), 0, s, z, x, xbar, P.Ntot, th + k);
+            KP_LAUNCH_CHECK();
+        }
+        if (op.objective_host) op.objective_host[k + 1] = objective(P, x, yint, op.reg, op.lambda, levels, s);
+    }
+    copy2(x, x_out, P.Ntot, s);
+    if (u_out) permute_to_caller(u, u_out, P.perm.as<int32_t>(), P.M, C, s);
+}
+
+}  // namespace kp
+
+using namespace kp;
+
+extern "C" {
+
+int pdhg_lambda_max(kp_plan_t plan, const float* p, int p_kind, int iters, float* out, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl || !out) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        if (iters < 1) fail(KP_ERR_INVALID_ARG, "iters must be >= 1");
+        Plan& P = *plan->impl;
+        check_p(P, p, p_kind);
+        hipStream_t s = (hipStream_t)stream;
+        const float* pint = load_p(P, p, p_kind, s);
+        power_method(P, pint, p_kind == KP_PRECOND_MC ? 1 : 0, iters, out, s);
+    });
+}
+
+int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind, const kp_pdhg_opts* opts, void* x_out,
+               void* u_out, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl || !opts || !y || !x_out) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        pdhg_solve_impl(*plan->impl, (const float2*)y, p, p_kind, *opts, (float2*)x_out, (float2*)u_out,
+                        (hipStream_t)stream);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+"""GPU parity of the plan, forward and adjoint NUFFT against the FP64 oracle.
+
+Bars: the sort (permutation, bin offsets, tile touch lists) and the float32
+canonical grid coordinates are bit-exact; floating-point outputs match within
+1e-4 relative L2 (typically ~1e-6).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import nufft as onufft
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _kp():
+    import paper_1902_09657_amd as kp
+    return kp
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def case(shape, C, M, seed, alpha, W, specials=True):
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    k = synth.random_coords(M, d, rng, specials=specials)
+    maps = synth.coil_maps(shape, C, rng) if C > 1 else None
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    y = rng.standard_normal((C, M)) + 1j * rng.standard_normal((C, M))
+    return k, maps, x, y
+
+
+CASES = [
+    # shape, C, M, alpha, W
+    ((40, 48), 3, 3000, 1.25, 4),
+    ((32, 32), 1, 1500, 2.0, 4),
+    ((30, 22), 2, 777, 2.0, 6),
+    ((16, 20, 24), 2, 4000, 1.25, 4),
+    ((12, 10, 8), 4, 1000, 2.0, 2),
+    ((24, 24), 8, 2049, 1.25, 8),
+]
+
+
+def _plan(kp, k, shape, maps, alpha, W, **kw):
+    m = None if maps is None else dev(maps, torch.complex64)
+    return kp.nufft_plan(dev(k, torch.float32), shape, m, oversamp=alpha, kb_width=W, **kw)
+
+
+@pytest.mark.parametrize("shape,C,M,alpha,W", CASES)
+def test_grid_coords_and_sort_bit_exact(shape, C, M, alpha, W):
+    kp = _kp()
+    k, maps, _, _ = case(shape, C, M, 11, alpha, W)
+    print("case", shape, C, M, alpha, W, flush=True)
+    plan = _plan(kp, k, shape, maps, alpha, W)
+    info = plan.info()
+    G = onufft.grid_shape(shape, alpha)
+    assert tuple(info["grid"]) == G
+    g_or = onufft.canonical_coords(k, G)
+    g_gpu = plan.grid_coords().cpu().numpy()
+    assert np.array_equal(g_gpu.view(np.uint32), g_or.view(np.uint32))
+    B = info["bin_size"]
+    perm_o, off_o = onufft.sort_by_bin(g_or, G, B)
+    perm, boff, toff, touch = [t.cpu().numpy() for t in plan.sort()]
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(boff, off_o)
+    toff_o, touch_o = onufft.tile_touch_lists(g_or[perm_o], G, B, W)
+    assert np.array_equal(toff, toff_o)
+    assert np.array_equal(touch, touch_o)
+    plan.close()
+
+
+@pytest.mark.parametrize("shape,C,M,alpha,W", CASES)
+def test_forward_adjoint_parity(shape, C, M, alpha, W):
+    kp = _kp()
+    k, maps, x, y = case(shape, C, M, 12, alpha, W)
+    print("case", shape, C, M, alpha, W, flush=True)
+    op = onufft.Nufft(k, shape, maps, alpha, W)
+    plan = _plan(kp, k, shape, maps, alpha, W)
+    yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
+    assert rel(yg, op.forward(x)) < 1e-4
+    xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
+    assert rel(xg, op.adjoint(y)) < 1e-4
+    plan.close()
+
+
+def test_heavy_tiles_split_path():
+    """Tiny chunks force every busy tile through the split (atomic) path."""
+    kp = _kp()
+    shape, C = (24, 28), 3
+    k, maps, x, y = case(shape, C, 2500, 13, 1.25, 4)
+    k[100:900] = 0.0                     # a dense centre
+    op = onufft.Nufft(k, shape, maps, 1.25, 4)
+    for chunk in (7, 64):
+        plan = _plan(kp, k, shape, maps, 1.25, 4, max_chunk=chunk, bin_size=(5, 6))
+        assert plan.info()["heavy_tiles"] > 0
+        xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
+        assert rel(xg, op.adjoint(y)) < 1e-4
+        yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
+        assert rel(yg, op.forward(x)) < 1e-4
+        plan.close()
+
+
+def test_adjoint_identity_on_gpu():
+    kp = _kp()
+    shape, C = (20, 24, 16), 3
+    k, maps, x, y = case(shape, C, 5000, 14, 1.25, 4)
+    plan = _plan(kp, k, shape, maps, 1.25, 4)
+    xt, yt = dev(x, torch.complex64), dev(y, torch.complex64)
+    ax = kp.nufft_forward(plan, xt)
+    ahy = kp.nufft_adjoint(plan, yt)
+    lhs = torch.vdot(ax.flatten().to(torch.complex128), yt.flatten().to(torch.complex128)).item()
+    rhs = torch.vdot(xt.flatten().to(torch.complex128), ahy.flatten().to(torch.complex128)).item()
+    assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
+    plan.close()
+
+
+def test_config1_radial_parity():
+    """128^2 single coil, 64 x 256 radial, alpha 2, W 4 (axis-aligned spokes, -pi)."""
+    kp = _kp()
+    cfg = synth.config(1)
+    x, maps, k, _ = cfg.inputs(1)
+    op = onufft.Nufft(k, cfg.shape, None, cfg.alpha, cfg.width)
+    plan = _plan(kp, k, cfg.shape, None, cfg.alpha, cfg.width)
+    yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
+    assert rel(yg, op.forward(x)) < 1e-4
+    yy = op.forward(x)
+    xg = kp.nufft_adjoint(plan, dev(yy, torch.complex64)).cpu().numpy()
+    assert rel(xg, op.adjoint(yy)) < 1e-4
+    perm, boff, _, _ = [t.cpu().numpy() for t in plan.sort()]
+    G = onufft.grid_shape(cfg.shape, cfg.alpha)
+    perm_o, off_o = onufft.sort_by_bin(onufft.canonical_coords(k, G), G, plan.info()["bin_size"])
+    assert np.array_equal(perm, perm_o) and np.array_equal(boff, off_o)
+    plan.close()
+
+
+def test_edge_cases():
+    kp = _kp()
+    # a single sample
+    shape = (8, 8)
+    k = np.zeros((1, 2), np.float32)
+    plan = _plan(kp, k, shape, None, 2.0, 4)
+    x = np.random.default_rng(0).standard_normal(shape) + 0j
+    op = onufft.Nufft(k, shape, None, 2.0, 4)
+    assert rel(kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy(), op.forward(x)) < 1e-4
+    plan.close()
+    # out-of-range and NaN coordinates are rejected
+    for bad in (np.array([[10.0, 0.0]], np.float32), np.array([[np.nan, 0.0]], np.float32)):
+        with pytest.raises(kp.KpError) as ei:
+            _plan(kp, bad, shape, None, 2.0, 4)
+        assert ei.value.code == -1
+    # coordinates slightly beyond pi wrap periodically
+    k2 = np.array([[math.pi + 0.3, -math.pi - 0.2], [0.1, 0.2]], np.float32)
+    plan = _plan(kp, k2, shape, None, 2.0, 4)
+    op = onufft.Nufft(k2, shape, None, 2.0, 4)
+    assert rel(kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy(), op.forward(x)) < 1e-4
+    plan.close()
