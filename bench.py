@@ -1,0 +1,245 @@
+"""Benchmark of the k-space-preconditioned PDHG hot path on one MI355X.
+
+Workload: 3D centre-out UTE radial, 160^3 complex64 image, 8 coils,
+20000 half-spokes x 128 samples (2.56 M samples per coil), oversampling
+1.25, Kaiser-Bessel width 4, l1-wavelet (db4, 4 levels, lambda 5e-3),
+multi-channel k-space preconditioner, 30 PDHG iterations.  Seeded synthetic
+inputs (random ellipsoids, Gaussian-blob coil maps with unit sum of squares,
+Fibonacci-sphere spokes, complex Gaussian noise sigma 1e-3); the k-space data
+come from a more accurate NUFFT (alpha 2, W 8) of the phantom plus noise.
+
+A timed step is one PDHG iteration (forward NUFFT with the fused dual
+update, adjoint NUFFT with the fused primal update, wavelet prox and
+extrapolation); K steps run as one pdhg_solve of K iterations with the
+preconditioner and lambda_max prepared beforehand (their build times are
+reported separately).  `value` is the NUFFT forward+adjoint throughput those
+steps achieve, in Msamples.coil/s: M C K / t.
+
+Prints one JSON line.  `python bench.py --gpus N --steps K --warmup W`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def byte_model(shape, G, C, M, d):
+    """Algorithmic HBM bytes of one forward + adjoint (grid-in-HBM model).
+
+    Forward per coil: read x share and s_c, pruned FFT passes (pass j writes
+    the array with axis d-1-j expanded N -> G; every later pass reads it
+    back), read grid + coordinates/permutation share, write y.  Adjoint: the
+    mirror image.  Returns a dict of per-kernel and total bytes.
+    """
+    N = list(shape)
+    Ntot = int(np.prod(N))
+    # forward passes: sizes after each pass (complex64 x C)
+    sizes = []
+    cur = list(N)
+    for p in range(d):
+        ax = d - 1 - p
+        cur[ax] = G[ax]
+        sizes.append(int(np.prod(cur)) * 8 * C)
+    fwd_fft = (Ntot * 8 + Ntot * 8 * C) + sizes[0]          # pass 1: read x, s; write
+    for p in range(1, d):
+        fwd_fft += sizes[p - 1] + sizes[p]
+    grid = int(np.prod(G)) * 8 * C
+    coords = M * (4 * d + 4)
+    interp = grid + coords + M * 8 * C
+    spread = M * 8 * C + coords + grid
+    adj_fft = fwd_fft                                         # mirror image
+    return {"fwd_fft": fwd_fft, "interp": interp, "spread": spread, "adj_fft": adj_fft,
+            "total": fwd_fft + interp + spread + adj_fft, "grid": grid}
+
+
+def cpu_baseline(cfg, k, x, maps):
+    """The FP64 oracle's NUFFT forward + adjoint on one coil of the workload."""
+    from oracle import nufft as onufft
+    t0 = time.perf_counter()
+    op = onufft.Nufft(k, cfg.shape, maps[:1], cfg.alpha, cfg.width)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    y = op.forward(x)
+    t1 = time.perf_counter()
+    op.adjoint(y)
+    t2 = time.perf_counter()
+    M = k.shape[0]
+    return {
+        "value": M / (t2 - t0) / 1e6, "unit": "Msamples*coil/s", "cores": 1, "kind": "oracle",
+        "sample": "one of 8 coils of the full workload (full 200^3 grid, all %d samples); "
+                  "forward %.1f s + adjoint %.1f s, tap setup %.1f s excluded; numpy FFT single-threaded"
+                  % (M, t1 - t0, t2 - t1, t_setup),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the per-GPU share is the "
+              "single-GPU workload); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1902_09657_amd as kp
+    from paper_1902_09657_amd import _lib
+    import synth
+
+    dev = torch.device("cuda:0")
+    cfg = synth.config(3)
+    d = cfg.ndim
+    log("generating inputs", cfg.name)
+    x, maps, k, w = cfg.inputs(seed=3)
+    M, C = k.shape[0], cfg.ncoils
+    xt = torch.from_numpy(x.astype(np.complex64)).to(dev)
+    mt = torch.from_numpy(maps.astype(np.complex64)).to(dev)
+    kt = torch.from_numpy(k).to(dev)
+    wt = torch.from_numpy(w.astype(np.complex64)).to(dev)
+    torch.cuda.synchronize()
+
+    # data: a more accurate NUFFT of the phantom plus noise
+    log("data")
+    hi = kp.nufft_plan(kt, cfg.shape, mt, oversamp=2.0, kb_width=8)
+    y = kp.nufft_forward(hi, xt) + wt
+    torch.cuda.synchronize()
+    hi.close()
+    del hi
+
+    log("plan")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info()
+    log("plan info", info)
+
+    log("precond")
+    t0 = time.perf_counter()
+    p = kp.precond_build(plan, kp.KP_PRECOND_MC)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+
+    log("lambda_max")
+    t0 = time.perf_counter()
+    lmax = kp.pdhg_lambda_max(plan, p, 30)
+    torch.cuda.synchronize()
+    t_lmax = time.perf_counter() - t0
+    lmax_v = float(lmax.item())
+
+    solve_kw = dict(reg=cfg.reg, lam=cfg.lam, wavelet_levels=4, lambda_max=lmax_v)
+    log("warmup")
+    if args.warmup > 0:
+        kp.pdhg_solve(plan, y, p, iters=args.warmup, **solve_kw)
+    torch.cuda.synchronize()
+
+    log("timed solve")
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    xr = kp.pdhg_solve(plan, y, p, iters=args.steps, **solve_kw)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t0
+    t_solve = e0.elapsed_time(e1) / 1e3
+    assert torch.isfinite(xr).all().item()
+
+    # plain NUFFT forward + adjoint pairs through the C ABI
+    log("nufft pairs")
+    xa = torch.empty_like(xt)
+    for _ in range(2):
+        kp.nufft_forward(plan, xt, y)
+        kp.nufft_adjoint(plan, y, xa)
+    R = 10
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(R):
+        kp.nufft_forward(plan, xt, y)
+        kp.nufft_adjoint(plan, y, xa)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_pair = e0.elapsed_time(e1) / 1e3 / R
+
+    # per-stage timings (HIP events around launches of one stage on this stream)
+    L = _lib.load()
+    sp = ctypes_stream(s)
+    stage_ms = {}
+    for name, st in [("fwd_fft", _lib.KP_STAGE_FWD_FFT), ("interp", _lib.KP_STAGE_INTERP),
+                     ("spread", _lib.KP_STAGE_SPREAD), ("adj_fft", _lib.KP_STAGE_ADJ_FFT)]:
+        _lib.check(L.nufft_stage(plan.handle, st, 2, sp))
+        torch.cuda.synchronize()
+        e0.record(s)
+        _lib.check(L.nufft_stage(plan.handle, st, args.kernel_reps, sp))
+        e1.record(s)
+        torch.cuda.synchronize()
+        stage_ms[name] = e0.elapsed_time(e1) / args.kernel_reps
+    bm = byte_model(cfg.shape, info["grid"], C, M, d)
+    dom = max(["interp", "spread"], key=lambda n: stage_ms[n])
+    achieved = bm[dom] / (stage_ms[dom] / 1e3) / 1e9
+
+    K = args.steps
+    value = M * C * K / t_solve / 1e6
+    result = {
+        "metric": "NUFFT fwd+adj Msamples*coil/s; PDHG iters/s; % HBM roofline vs plain form",
+        "value": round(value, 2),
+        "unit": "Msamples*coil/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_solve / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "image": list(cfg.shape), "coils": C, "samples_per_coil": M,
+                   "oversamp": cfg.alpha, "kb_width": cfg.width, "reg": "l1-db4-4lev", "lambda": cfg.lam,
+                   "precond": "mc", "iters": K},
+        "pdhg_iters_per_s": round(K / t_solve, 2),
+        "nufft_pair_ms": round(t_pair * 1e3, 4),
+        "nufft_pair_msamples_coil_per_s": round(M * C / t_pair / 1e6, 2),
+        "nufft_pair_hbm_roofline_frac": round(bm["total"] / t_pair / 1e9 / HBM_PEAK_GBS, 4),
+        "stage_ms": {k2: round(v, 4) for k2, v in stage_ms.items()},
+        "setup_s": {"plan": round(t_plan, 4), "precond_mc": round(t_pre, 4), "lambda_max_30": round(t_lmax, 4)},
+        "lambda_max": lmax_v,
+        "wall_s_timed": round(t_wall, 4),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    plan.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one coil)")
+        result["cpu_baseline"] = cpu_baseline(cfg, k, x, maps)
+    print(json.dumps(result), flush=True)
+
+
+def ctypes_stream(s):
+    import ctypes
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+if __name__ == "__main__":
+    main()

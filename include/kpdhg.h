@@ -200,6 +200,16 @@ int nufft_plan_validate(int ndim, const int64_t* shape, int64_t ncoils, int64_t 
                         const void* coords, const void* maps, float oversamp, int kb_width,
                         const kp_tuning* tuning);
 
+/* Profiling aid: run one stage of the NUFFT `reps` times on the plan's own
+ * workspaces (their contents are whatever the last call left), so that a
+ * timer around it sees that stage alone.
+ *   KP_STAGE_FWD_FFT  pre-pass + pruned forward FFT passes (d kernels)
+ *   KP_STAGE_INTERP   Kaiser-Bessel interpolation into internal k-space
+ *   KP_STAGE_SPREAD   tile spreading of internal k-space onto the grid
+ *   KP_STAGE_ADJ_FFT  pruned inverse FFT passes + post-pass (d kernels) */
+enum { KP_STAGE_FWD_FFT = 0, KP_STAGE_INTERP = 1, KP_STAGE_SPREAD = 2, KP_STAGE_ADJ_FFT = 3 };
+int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream);
+
 /* Thread-local message of the last failure (valid until the next call). */
 const char* kp_last_error(void);
 

@@ -26,8 +26,9 @@ EXPORTS = [
     "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
     "pdhg_solve", "pdhg_unrolled_ckpt_bytes", "pdhg_unrolled_forward", "pdhg_unrolled_backward",
     "nufft_destroy", "nufft_plan_info", "nufft_plan_sort", "nufft_plan_grid_coords",
-    "kp_db4_filter", "nufft_plan_validate", "kp_last_error",
+    "kp_db4_filter", "nufft_plan_validate", "kp_last_error", "nufft_stage",
 ]
+KP_STAGE_FWD_FFT, KP_STAGE_INTERP, KP_STAGE_SPREAD, KP_STAGE_ADJ_FFT = 0, 1, 2, 3
 
 
 class KpError(RuntimeError):
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
         "kp_db4_filter": (i32, [P(ctypes.c_double)]),
         "nufft_plan_validate": (i32, [i32, P(i64), i64, i64, vp, vp, f32, i32, P(Tuning)]),
         "kp_last_error": (ctypes.c_char_p, []),
+        "nufft_stage": (i32, [vp, i32, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -931,6 +931,32 @@ int nufft_plan_grid_coords(kp_plan_t plan, float* g, void* stream) {
     });
 }
 
+int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
+        if (stage < 0 || stage > 3) fail(KP_ERR_INVALID_ARG, "unknown stage");
+        if (reps < 1) fail(KP_ERR_INVALID_ARG, "reps must be >= 1");
+        Plan& P = *plan->impl;
+        hipStream_t s = (hipStream_t)stream;
+        for (int r = 0; r < reps; ++r) {
+            if (stage == KP_STAGE_FWD_FFT) {
+                FwdOpts fo;
+                forward_to_grid(P, P.img[0].as<float2>(), fo, s);
+            } else if (stage == KP_STAGE_INTERP) {
+                InterpArgs ia{};
+                ia.mode = IO_INTERNAL;
+                ia.out = P.kint3.as<float2>();
+                interp(P, P.d % 2 ? P.bufA.as<float2>() : P.bufB.as<float2>(), ia, s);
+            } else if (stage == KP_STAGE_SPREAD) {
+                spread_to_grid(P, P.kint.as<float2>(), (int)P.C, s);
+            } else {
+                AdjOpts ao;
+                grid_to_image(P, P.bufA.as<float2>(), P.img[3].as<float2>(), ao, s);
+            }
+        }
+    });
+}
+
 int kp_db4_filter(double* h8) {
     return guarded([&] {
         if (!h8) fail(KP_ERR_INVALID_ARG, "h8 is NULL");
