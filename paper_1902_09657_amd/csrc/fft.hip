@@ -269,9 +269,225 @@ static int lds_limit() {
     return lim;
 }
 
+// ------------------------------------------------------------------------
+// Specialised pass for the transform lengths of the benchmark workloads: the
+// length, the radix sequence and the column block (NC = 8 or 16 columns, a
+// divisor of the 256 threads, so every thread keeps one column) are compile
+// time constants, every index is a shift or a multiply, and the stages run
+// in place in a single LDS buffer with the butterfly inputs held in
+// registers across the barrier.
+constexpr int fft_radix_c(int L, int s) {
+    int r = L, n = 0;
+    int rad[16] = {};
+    while (r % 8 == 0 && r > 8) { rad[n++] = 8; r /= 8; }
+    while (r % 4 == 0) { rad[n++] = 4; r /= 4; }
+    while (r % 2 == 0) { rad[n++] = 2; r /= 2; }
+    while (r % 5 == 0) { rad[n++] = 5; r /= 5; }
+    while (r % 3 == 0) { rad[n++] = 3; r /= 3; }
+    return s < n ? rad[s] : 1;
+}
+constexpr int fft_span_c(int L, int s) {  // product of the radices before stage s
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= fft_radix_c(L, i);
+    return p;
+}
+
+template <int R>
+__device__ __forceinline__ void dft_c(float2* v, int inv) {
+    if (R == 2) dft2(v);
+    else if (R == 3) dft3(v, inv);
+    else if (R == 4) dft4(v, inv);
+    else if (R == 5) dft5(v, inv);
+    else dft8(v, inv);
+}
+
+template <int L, int NC, int S>
+__device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restrict__ tw, int inv, int tid) {
+    constexpr int R = fft_radix_c(L, S);
+    if (R == 1) return;
+    constexpr int NS = fft_span_c(L, S);
+    constexpr int NBF = L / R;
+    constexpr int TOT = NBF * NC;
+    constexpr int NB = (TOT + 255) / 256;
+    constexpr int STRIDE = L / (NS * R);
+    const int col = tid % NC;
+    float2 v[NB][R];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int j = tid / NC + k * (256 / NC);
+        if (k * 256 + tid < TOT) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[k][t] = buf[(j + t * NBF) * NC + col];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int j = tid / NC + k * (256 / NC);
+        if (k * 256 + tid < TOT) {
+            const int kk = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    float2 w = tw[t * kk * STRIDE];
+                    if (inv) w.y = -w.y;
+                    v[k][t] = cmul(v[k][t], w);
+                }
+            }
+            dft_c<R>(v[k], inv);
+            const int base = (j / NS) * NS * R + kk;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[(base + t * NS) * NC + col] = v[k][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <int L, int NC>
+__global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
+    extern __shared__ float2 buf[];
+    constexpr int RS = 256 / NC;  // rows per sweep of the block
+    const int tid = threadIdx.x;
+    const int col = tid % NC, rb = tid / NC;
+    const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
+    const int64_t bid = blockIdx.x;
+    const int64_t o0 = (bid / nIb) * p.Ob;
+    const int64_t i0 = (bid % nIb) * p.Ib;
+    const int64_t o = o0 + col / p.Ib, i = i0 + col % p.Ib;
+    const bool live = o < p.O && i < p.I;
+    const float xs = p.xscale ? *p.xscale : 1.f;
+
+    // ---- load (pruned)
+    if (p.pad_in) {
+        const int g0 = p.Lin / 2, g1 = L - p.Lin + p.Lin / 2;
+        for (int q = g0 + rb; q < g1; q += RS) buf[q * NC + col] = make_float2(0.f, 0.f);
+    }
+    for (int r = rb; r < p.Lin; r += RS) {
+        float2 v = make_float2(0.f, 0.f);
+        if (live) {
+            if (p.pre == PRE_NONE) {
+                v = p.in[o * p.in_os + r * p.in_rs + i];
+            } else if (p.pre == PRE_MAPS) {
+                const int64_t e = o * p.Lin + r;
+                v = cscale(cmul(p.px[e], p.pmaps[e * p.I + i]), p.fo[o] * p.fr[r] * xs);
+            } else {
+                const int64_t e = o * p.Lin + r;
+                v = cscale(p.px[e * p.I + i], p.fo[o] * p.fr[r] * xs);
+            }
+        }
+        int pos = r;
+        if (p.pad_in) {
+            pos = r - p.Lin / 2;
+            pos += pos < 0 ? L : 0;
+        }
+        buf[pos * NC + col] = v;
+    }
+    __syncthreads();
+
+    fixed_stage<L, NC, 0>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 1>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 2>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 3>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 4>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 5>(buf, p.tw, p.inverse, tid);
+
+    // ---- store (pruned)
+    if (p.post == POST_MAPS) {
+        const int C = p.Ib;
+        const int tpo = 256 / p.Ob;  // threads per outer
+        const int ol = tid / tpo;
+        const int64_t oo = o0 + ol;
+        if (ol >= p.Ob || oo >= p.O) return;
+        for (int m = tid % tpo; m < p.Lout; m += tpo) {
+            int q = m;
+            if (p.crop_out) {
+                q = m - p.Lout / 2;
+                q += q < 0 ? L : 0;
+            }
+            const int64_t e = oo * p.Lout + m;
+            const float2* mp = p.qmaps + e * C;
+            const float2* row = buf + q * NC + ol * C;
+            float2 acc = make_float2(0.f, 0.f);
+            for (int c = 0; c < C; ++c) acc = cadd(acc, cmulc(row[c], mp[c]));
+            acc = cscale(acc, p.fo[oo] * p.fr[m]);
+            if (p.epi == EPI_STORE) {
+                p.qx[e] = acc;
+            } else if (p.epi == EPI_L2) {
+                const float tau = *p.e_tau, th = *p.e_theta;
+                const float2 xo = p.ex[e];
+                const float den = 1.f / (1.f + tau * p.e_lambda);
+                const float2 xn = make_float2((xo.x - tau * acc.x) * den, (xo.y - tau * acc.y) * den);
+                p.exbar[e] = make_float2(xn.x + th * (xn.x - xo.x), xn.y + th * (xn.y - xo.y));
+                p.ex[e] = xn;
+            } else {
+                const float tau = *p.e_tau;
+                const float2 xo = p.ex[e];
+                p.exbar[e] = make_float2(xo.x - tau * acc.x, xo.y - tau * acc.y);
+            }
+        }
+        return;
+    }
+    if (!live) return;
+    for (int m = rb; m < p.Lout; m += RS) {
+        int q = m;
+        if (p.crop_out) {
+            q = m - p.Lout / 2;
+            q += q < 0 ? L : 0;
+        }
+        const float2 v = buf[q * NC + col];
+        if (p.post == POST_NONE) {
+            p.out[o * p.out_os + m * p.out_rs + i] = v;
+        } else {
+            const int64_t e = o * p.Lout + m;
+            p.qx[e * p.I + i] = cscale(v, p.fo[o] * p.fr[m]);
+        }
+    }
+}
+
+typedef void (*fft_kernel_t)(FftPass);
+
+template <int NC>
+static fft_kernel_t fixed_for(int L) {
+    switch (L) {
+        case 160: return k_fft_fixed<160, NC>;
+        case 200: return k_fft_fixed<200, NC>;
+        case 240: return k_fft_fixed<240, NC>;
+        case 256: return k_fft_fixed<256, NC>;
+        case 320: return k_fft_fixed<320, NC>;
+        case 400: return k_fft_fixed<400, NC>;
+        case 512: return k_fft_fixed<512, NC>;
+        case 640: return k_fft_fixed<640, NC>;
+        default: return nullptr;
+    }
+}
+
+// try the specialised kernel; false if this pass does not fit it
+static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
+    const int nc = p.Ob * p.Ib;
+    if (nc != 8 && nc != 16) return false;
+    if (p.post == POST_MAPS && (256 % p.Ob) != 0) return false;
+    fft_kernel_t fn = nc == 16 ? fixed_for<16>(p.L) : fixed_for<8>(p.L);
+    if (!fn) return false;
+    const size_t lds = sizeof(float2) * (size_t)p.L * nc;
+    if (lds > (size_t)lim) return false;
+    if (lds > 65536) {
+        (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipGetLastError();
+    }
+    const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
+    const int64_t nOb = (p.O + p.Ob - 1) / p.Ob;
+    const int64_t nblk = nIb * nOb;
+    if (nblk <= 0) return true;
+    if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "FFT pass grid too large");
+    hipLaunchKernelGGL(fn, dim3((unsigned)nblk), dim3(256), lds, s, p);
+    KP_LAUNCH_CHECK();
+    return true;
+}
+
 void launch_fft_pass(const FftPass& pin, hipStream_t s) {
     FftPass p = pin;
     const int lim = lds_limit();
+    if (launch_fixed(p, s, lim)) return;
     // shrink the column block until both LDS buffers fit
     while (fft_lds_bytes(p.L, p.Ob * p.Ib) > (size_t)lim) {
         if (p.Ob > 1)

@@ -1,73 +1,106 @@
 // Kaiser-Bessel interpolation (forward, gather) and spreading (adjoint).
 //
 // Grid layout [G_0][G_1]([G_2])[C]: the C coils of one grid cell are
-// contiguous, so every tap of every sample reads or writes one contiguous
-// C-vector, and the per-axis kernel weights of a sample are computed once
-// and shared by all coils.
+// contiguous, so every tap of a sample reads or writes one contiguous
+// C-vector and the per-axis kernel weights of a sample are shared by all
+// coils.
 //
-// Weights: C(u) = I0(beta sqrt(1 - (2u/W)^2)) / W for |u| < W/2, with I0
-// from its power series sum_k (x^2/4)^k / (k!)^2 summed term by term
-// (a_k = a_{k-1} t / k^2, all terms positive).  Taps of a sample at grid
-// coordinate g: j = floor(g) - W/2 + 1 + t, u = g - j, t = 0..W-1, taken
-// modulo G.
+// Weights: C(u) = I0(beta sqrt(1 - (2u/W)^2)) / W for |u| < W/2.  The taps of
+// a sample at grid coordinate g are j = floor(g) - W/2 + 1 + t, u = g - j,
+// t = 0..W-1 (modulo G).  As a function of x = frac(g) - 1/2 the weight of
+// tap t is smooth on [0, 1), so each tap's weight is a degree-9 polynomial in
+// x fitted on the host (Chebyshev nodes, double precision; about 1e-7 of the
+// peak in float32).  The last tap at frac(g) = 0 sits exactly on the support
+// edge |u| = W/2 and weighs 0.
 //
-// Spreading never uses global atomics for an ordinary tile: every tile of
-// the grid is owned by one work item, which gathers every sample whose
-// footprint meets the tile (its touch list), accumulates the weighted values
-// in an LDS copy of the tile, then stores the tile.  Tiles with more touch
-// entries than a work item takes (the dense k-space centre) are split over
-// several work items that add their LDS tiles into a pre-zeroed grid region.
+// Spreading is gather-by-owner: every tile of the grid is owned by one work
+// item, which takes every sample whose footprint meets the tile (its touch
+// list) in chunks staged in LDS, buckets the chunk by the sample's first
+// tap along the leading axes, and lets each thread own one line of the tile
+// along the last axis (and a group of coils) in registers.  A thread visits
+// exactly the samples that cover its line, so there are no atomics at all
+// for an owned tile; a tile whose touch list was split over several work
+// items (the dense k-space centre) adds its registers into a pre-zeroed grid
+// region with global float atomics.
+#include <algorithm>
+#include <cmath>
+
 #include "kp_internal.h"
 
 namespace kp {
 
-__constant__ float c_inv_k2[96];
-
-void upload_kb_constants() {
-    static bool done = false;
-    if (done) return;
-    float h[96];
-    h[0] = 1.f;
-    for (int k = 1; k < 96; ++k) h[k] = (float)(1.0 / ((double)k * (double)k));
-    KP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_inv_k2), h, sizeof(h)));
-    done = true;
-}
-
-int nterms_for(double beta2_4) {
-    // smallest K with the series tail below 1e-9 of the sum at the largest
-    // argument t = beta^2/4
-    double t = beta2_4, a = 1.0, s = 1.0;
-    int k = 1;
-    for (; k < 95; ++k) {
+// ------------------------------------------------------------ KB weights
+double kb_kernel_host(double u, int W, double beta) {
+    const double half = W / 2.0;
+    if (!(std::fabs(u) < half)) return 0.0;
+    const double r = u / half;
+    const double t = beta * beta * (1.0 - r * r) / 4.0;  // (x/2)^2
+    // I0(x) = sum_k t^k / (k!)^2, terms positive
+    double a = 1.0, s = 1.0;
+    for (int k = 1; k < 200; ++k) {
         a *= t / ((double)k * k);
         s += a;
-        if (a < 1e-10 * s && (double)k * k > t) break;
+        if (a < 1e-18 * s) break;
     }
-    return k + 1 < 95 ? k + 1 : 95;
+    return s / W;
+}
+
+void kb_fit(double beta, int W, KbParams* kb) {
+    const int n = kPolyN;
+    double nodes[kPolyN];
+    for (int i = 0; i < n; ++i) nodes[i] = 0.5 * std::cos((2.0 * i + 1.0) * M_PI / (2.0 * n));
+    for (int t = 0; t < 8; ++t)
+        for (int k = 0; k < n; ++k) kb->poly[t][k] = 0.f;
+    for (int t = 0; t < W; ++t) {
+        // interpolate f_t(x) = C(x + 1/2 + W/2 - 1 - t) at the nodes (Vandermonde, partial pivoting)
+        double A[kPolyN][kPolyN + 1];
+        for (int i = 0; i < n; ++i) {
+            double p = 1.0;
+            for (int k = 0; k < n; ++k) {
+                A[i][k] = p;
+                p *= nodes[i];
+            }
+            double u = nodes[i] + 0.5 + W / 2.0 - 1.0 - t;
+            // the last tap's weight tends to C(-W/2 + 0) = 1/W as frac -> 0+
+            if (t == W - 1) u = std::max(u, -W / 2.0 + 1e-300);
+            A[i][n] = kb_kernel_host(u, W, beta);
+            if (t == W - 1 && !(std::fabs(u) < W / 2.0)) A[i][n] = 1.0 / W;
+        }
+        for (int c = 0; c < n; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < n; ++r)
+                if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+            for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
+            for (int r = 0; r < n; ++r) {
+                if (r == c) continue;
+                const double f = A[r][c] / A[c][c];
+                for (int k = c; k <= n; ++k) A[r][k] -= f * A[c][k];
+            }
+        }
+        for (int k = 0; k < n; ++k) kb->poly[t][k] = (float)(A[k][n] / A[k][k]);
+    }
 }
 
 template <int W>
-__device__ __forceinline__ float kb_weight(float u, const KbParams& kb) {
-    if (u <= -(float)(W / 2)) return 0.f;  // strict support |u| < W/2
-    const float r = u * kb.inv_half;
-    const float arg = fmaxf(1.f - r * r, 0.f);
-    const float t = kb.beta2_4 * arg;
-    float term = 1.f, sum = 1.f;
-    for (int k = 1; k < kb.nterms; ++k) {
-        term *= t * c_inv_k2[k];
-        sum += term;
+__device__ __forceinline__ void tap_weights(float frac, const KbParams& kb, float* w) {
+    const float x = frac - 0.5f;
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        float acc = kb.poly[t][kPolyN - 1];
+#pragma unroll
+        for (int k = kPolyN - 2; k >= 0; --k) acc = fmaf(acc, x, kb.poly[t][k]);
+        w[t] = acc;
     }
-    return sum * kb.inv_w;
+    if (frac == 0.f) w[W - 1] = 0.f;  // strict support |u| < W/2
 }
 
 template <int W>
 __device__ __forceinline__ void axis_taps(float g, int Ga, const KbParams& kb, float* w, int* j) {
     const float cf = floorf(g);
     const int cell = (int)cf;
-    const float frac = g - cf;
+    tap_weights<W>(g - cf, kb, w);
 #pragma unroll
     for (int t = 0; t < W; ++t) {
-        w[t] = kb_weight<W>(frac + (float)(W / 2 - 1 - t), kb);
         int jj = cell - W / 2 + 1 + t;
         jj = jj < 0 ? jj + Ga : (jj >= Ga ? jj - Ga : jj);
         j[t] = jj;
@@ -75,91 +108,94 @@ __device__ __forceinline__ void axis_taps(float g, int Ga, const KbParams& kb, f
 }
 
 // ------------------------------------------------------------ interpolation
+// One thread per (sorted sample, group of CH coils), coil group fastest, so
+// the lanes of one sample read one contiguous C-vector per tap.
 template <int D, int W, int CH>
 __global__ void __launch_bounds__(256) k_interp(InterpArgs a, KbParams kb) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.M) return;
+    const int ncg = a.C / CH;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.M * ncg) return;
+    const int64_t s = gid / ncg;
+    const int c0 = (int)(gid % ncg) * CH;
+    const int C = a.C;
     float w[D][W];
     int jx[D][W];
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) axis_taps<W>(a.g[s * D + ax], a.G[ax], kb, w[ax], jx[ax]);
-    const int C = a.C;
-    for (int c0 = 0; c0 < C; c0 += CH) {
-        float2 acc[CH];
+    float2 acc[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] = make_float2(0.f, 0.f);
-        if (D == 2) {
+    for (int c = 0; c < CH; ++c) acc[c] = make_float2(0.f, 0.f);
+    if (D == 2) {
 #pragma unroll
-            for (int t0 = 0; t0 < W; ++t0) {
-                const int64_t r0 = (int64_t)jx[0][t0] * a.G[1];
+        for (int t0 = 0; t0 < W; ++t0) {
+            const int64_t r0 = (int64_t)jx[0][t0] * a.G[1];
 #pragma unroll
-                for (int t1 = 0; t1 < W; ++t1) {
-                    const float wt = w[0][t0] * w[1][t1];
-                    const float2* src = a.grid + (r0 + jx[1][t1]) * C + c0;
+            for (int t1 = 0; t1 < W; ++t1) {
+                const float wt = w[0][t0] * w[1][t1];
+                const float2* src = a.grid + (r0 + jx[1][t1]) * C + c0;
 #pragma unroll
-                    for (int c = 0; c < CH; ++c) {
-                        if (c0 + c < C) {
-                            float2 v = src[c];
-                            acc[c].x += wt * v.x;
-                            acc[c].y += wt * v.y;
-                        }
-                    }
+                for (int c = 0; c < CH; ++c) {
+                    const float2 v = src[c];
+                    acc[c].x += wt * v.x;
+                    acc[c].y += wt * v.y;
                 }
             }
-        } else {
+        }
+    } else {
+#pragma unroll 1
+        for (int t0 = 0; t0 < W; ++t0) {
+            const int64_t r0 = (int64_t)jx[0][t0] * a.G[1];
+            float wa = w[0][0];
 #pragma unroll
-            for (int t0 = 0; t0 < W; ++t0) {
-                const int64_t r0 = (int64_t)jx[0][t0] * a.G[1];
+            for (int q = 1; q < W; ++q) wa = (t0 == q) ? w[0][q] : wa;
 #pragma unroll
-                for (int t1 = 0; t1 < W; ++t1) {
-                    const int64_t r1 = (r0 + jx[1][t1]) * a.G[2];
-                    const float w01 = w[0][t0] * w[1][t1];
+            for (int t1 = 0; t1 < W; ++t1) {
+                const int64_t r1 = (r0 + jx[1][t1]) * a.G[2];
+                const float w01 = wa * w[1][t1];
 #pragma unroll
-                    for (int t2 = 0; t2 < W; ++t2) {
-                        const float wt = w01 * w[2][t2];
-                        const float2* src = a.grid + (r1 + jx[2][t2]) * C + c0;
+                for (int t2 = 0; t2 < W; ++t2) {
+                    const float wt = w01 * w[2][t2];
+                    const float2* src = a.grid + (r1 + jx[2][t2]) * C + c0;
 #pragma unroll
-                        for (int c = 0; c < CH; ++c) {
-                            if (c0 + c < C) {
-                                float2 v = src[c];
-                                acc[c].x += wt * v.x;
-                                acc[c].y += wt * v.y;
-                            }
-                        }
+                    for (int c = 0; c < CH; ++c) {
+                        const float2 v = src[c];
+                        acc[c].x += wt * v.x;
+                        acc[c].y += wt * v.y;
                     }
                 }
             }
         }
-        // epilogue
+    }
+    // epilogue
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int cc = c0 + c;
-            if (cc >= C) break;
-            const int64_t e = s * C + cc;
-            if (a.mode == IO_CALLER) {
-                a.out[(int64_t)cc * a.M + a.perm[s]] = acc[c];
-            } else if (a.mode == IO_INTERNAL) {
-                a.out[e] = acc[c];
-            } else if (a.mode == IO_PMUL) {
-                const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-                a.out[e] = make_float2(pv * acc[c].x, pv * acc[c].y);
-            } else {  // IO_DUAL
-                const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-                const float sp = *a.sigma * pv;
-                const float den = 1.f / (1.f + sp);
-                const float2 u = a.u[e], y = a.y[e];
-                a.u[e] = make_float2((u.x + sp * (acc[c].x - y.x)) * den, (u.y + sp * (acc[c].y - y.y)) * den);
-            }
+    for (int c = 0; c < CH; ++c) {
+        const int cc = c0 + c;
+        const int64_t e = s * C + cc;
+        if (a.mode == IO_CALLER) {
+            a.out[(int64_t)cc * a.M + a.perm[s]] = acc[c];
+        } else if (a.mode == IO_INTERNAL) {
+            a.out[e] = acc[c];
+        } else if (a.mode == IO_PMUL) {
+            const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+            a.out[e] = make_float2(pv * acc[c].x, pv * acc[c].y);
+        } else {  // IO_DUAL
+            const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+            const float sp = *a.sigma * pv;
+            const float den = 1.f / (1.f + sp);
+            const float2 u = a.u[e], y = a.y[e];
+            a.u[e] = make_float2((u.x + sp * (acc[c].x - y.x)) * den, (u.y + sp * (acc[c].y - y.y)) * den);
         }
     }
 }
 
 template <int D, int W>
 static void interp_dispatch_ch(const InterpArgs& a, const KbParams& kb, hipStream_t s) {
-    const unsigned nblk = (unsigned)((a.M + 255) / 256);
-    if (a.C % 4 == 0)
+    const int CH = a.C % 4 == 0 ? 4 : (a.C % 2 == 0 ? 2 : 1);
+    const int64_t n = a.M * (a.C / CH);
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    if (CH == 4)
         hipLaunchKernelGGL((k_interp<D, W, 4>), dim3(nblk), dim3(256), 0, s, a, kb);
-    else if (a.C % 2 == 0)
+    else if (CH == 2)
         hipLaunchKernelGGL((k_interp<D, W, 2>), dim3(nblk), dim3(256), 0, s, a, kb);
     else
         hipLaunchKernelGGL((k_interp<D, W, 1>), dim3(nblk), dim3(256), 0, s, a, kb);
@@ -177,12 +213,47 @@ void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStr
 }
 
 // ------------------------------------------------------------ spreading
-template <int D, int W>
+static int coil_group(int C) { return C % 4 == 0 ? 4 : (C % 2 == 0 ? 2 : 1); }
+
+int spread_threads(int d, const int* B, int C) {
+    const int lines = d == 3 ? B[0] * B[1] : B[0];
+    return lines * (C / coil_group(C));
+}
+
+// LDS carve-up for a chunk of E entries (all 4-byte words):
+//   code[E] | wl[(d-1) W][E] | wz[kZMax][E] | u[C][E] (float2) | order[E] | bstart[NBK+1] | cursor[NBK]
+// (entry index fastest, so lanes reading different entries hit different banks)
+static int spread_nbk(int d, int W, const int* B) {
+    return d == 3 ? (B[0] + W - 1) * (B[1] + W - 1) : (B[0] + W - 1);
+}
+size_t spread_lds_bytes(int d, int W, const int* B, int C) {
+    const size_t E = kSpreadChunk;
+    const size_t nbk = (size_t)spread_nbk(d, W, B);
+    const size_t words = E * (1 + (size_t)(d - 1) * W + kZMax + 2 * (size_t)C + 1) + nbk + 1 + std::max<size_t>(nbk, 256);
+    return 4 * words;
+}
+
+template <int D, int W, int CG>
 __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
-    extern __shared__ float sm[];
+    extern __shared__ int smem[];
+    constexpr int E = kSpreadChunk;
+    constexpr int NLW = (D - 1) * W;  // leading-axis weights per entry
+    const int C = a.C;
+    const int B0 = a.B[0];
+    const int B1 = D == 3 ? a.B[1] : 1;
+    const int ZL = a.B[D - 1];
+    const int NB1 = D == 3 ? B1 + W - 1 : 1;
+    const int NBK = D == 3 ? (B0 + W - 1) * NB1 : (B0 + W - 1);
+    int* code = smem;
+    float* wl = (float*)(code + E);
+    float* wz = wl + E * NLW;
+    float2* uu = (float2*)(wz + E * kZMax);
+    int* order = (int*)(uu + E * C);
+    int* bstart = order + E;
+    int* cursor = bstart + NBK + 1;
+
     const int4 wk = a.work[blockIdx.x];
     const int tile = wk.x, start = wk.y, count = wk.z, atomic = wk.w;
-    const int C = a.C;
     int tc[3] = {0, 0, 0};
     {
         int rem = tile;
@@ -191,104 +262,178 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
             rem /= a.nb[ax];
         }
     }
-    const int Bt = a.B[0] * a.B[1] * (D == 3 ? a.B[2] : 1);
-    float* re = sm;
-    float* im = sm + Bt * C;
-    for (int i = threadIdx.x; i < 2 * Bt * C; i += blockDim.x) sm[i] = 0.f;
-    __syncthreads();
+    int org[3];
+    for (int ax = 0; ax < D; ++ax) org[ax] = tc[ax] * a.B[ax];
 
-    for (int e = threadIdx.x; e < count; e += blockDim.x) {
-        const int s = a.touch[start + e];
-        float w[D][W];
-        int loc[D][W];
+    const int ncg = C / CG;
+    const int nthr = (D == 3 ? B0 * B1 : B0) * ncg;
+    const int tid = threadIdx.x;
+    const bool owner = tid < nthr;
+    const int line = tid / ncg, cg = tid % ncg;
+    const int j0 = D == 3 ? line / B1 : line;
+    const int j1 = D == 3 ? line % B1 : 0;
+
+    float2 acc[kZMax][CG];
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-            int jj[W];
-            axis_taps<W>(a.g[(int64_t)s * D + ax], a.G[ax], kb, w[ax], jj);
-            const int org = tc[ax] * a.B[ax];
+    for (int z = 0; z < kZMax; ++z)
 #pragma unroll
-            for (int t = 0; t < W; ++t) {
-                const int l = jj[t] - org;
-                loc[ax][t] = (l >= 0 && l < a.B[ax]) ? l : -1;
-            }
-        }
-        const float2* kv = a.k + (int64_t)s * C;
-        if (D == 2) {
+        for (int c = 0; c < CG; ++c) acc[z][c] = make_float2(0.f, 0.f);
+
+    for (int c0 = 0; c0 < count; c0 += E) {
+        const int n = min(E, count - c0);
+        // ---- A: stage the chunk: bucket code, weights, coil values
+        for (int i = tid; i <= NBK; i += blockDim.x) bstart[i] = 0;
+        __syncthreads();
+        for (int e = tid; e < n; e += blockDim.x) {
+            const int s = a.touch[start + c0 + e];
+            int bk = 0;
 #pragma unroll
-            for (int t0 = 0; t0 < W; ++t0) {
-                if (loc[0][t0] < 0) continue;
+            for (int ax = 0; ax < D; ++ax) {
+                const float g = a.g[(int64_t)s * D + ax];
+                const float cf = floorf(g);
+                float w[W];
+                tap_weights<W>(g - cf, kb, w);
+                const int Ga = a.G[ax];
+                int l = (int)cf - W / 2 + 1 - org[ax];
+                if (l < -(W - 1)) l += Ga;
+                else if (l > a.B[ax] - 1) l -= Ga;
+                if (ax < D - 1) {
 #pragma unroll
-                for (int t1 = 0; t1 < W; ++t1) {
-                    if (loc[1][t1] < 0) continue;
-                    const float wt = w[0][t0] * w[1][t1];
-                    const int l = (loc[0][t0] * a.B[1] + loc[1][t1]) * C;
-                    for (int c = 0; c < C; ++c) {
-                        const float2 v = kv[c];
-                        atomicAdd(&re[l + c], wt * v.x);
-                        atomicAdd(&im[l + c], wt * v.y);
+                    for (int t = 0; t < W; ++t) wl[(ax * W + t) * E + e] = w[t];
+                    bk = (ax == 0) ? (l + W - 1) : bk * NB1 + (l + W - 1);
+                } else {
+#pragma unroll
+                    for (int z = 0; z < kZMax; ++z) {
+                        const int t = z - l;
+                        float v = 0.f;
+#pragma unroll
+                        for (int q = 0; q < W; ++q) v = (t == q) ? w[q] : v;
+                        wz[z * E + e] = (z < ZL) ? v : 0.f;
                     }
                 }
             }
-        } else {
-#pragma unroll
-            for (int t0 = 0; t0 < W; ++t0) {
-                if (loc[0][t0] < 0) continue;
-#pragma unroll
-                for (int t1 = 0; t1 < W; ++t1) {
-                    if (loc[1][t1] < 0) continue;
-                    const float w01 = w[0][t0] * w[1][t1];
-                    const int l01 = (loc[0][t0] * a.B[1] + loc[1][t1]) * a.B[2];
-#pragma unroll
-                    for (int t2 = 0; t2 < W; ++t2) {
-                        if (loc[2][t2] < 0) continue;
-                        const float wt = w01 * w[2][t2];
-                        const int l = (l01 + loc[2][t2]) * C;
-                        for (int c = 0; c < C; ++c) {
-                            const float2 v = kv[c];
-                            atomicAdd(&re[l + c], wt * v.x);
-                            atomicAdd(&im[l + c], wt * v.y);
-                        }
-                    }
-                }
+            // low 16 bits: bucket; high bits: axis-1 bucket coordinate (3D)
+            code[e] = bk | ((D == 3 ? bk % NB1 : 0) << 16);
+            const float2* src = a.k + (int64_t)s * C;
+            for (int c = 0; c < C; ++c) uu[c * E + e] = src[c];
+            atomicAdd(&bstart[bk + 1], 1);
+        }
+        __syncthreads();
+        // ---- B: bucket offsets (exclusive scan) and counting-sort scatter
+        {
+            // inclusive scan of bstart[0..NBK] (bstart[0] = 0): each thread
+            // sums a run of buckets, then a Hillis-Steele scan of the run sums
+            const int nt = blockDim.x;
+            const int per = (NBK + 1 + nt - 1) / nt;
+            const int b0 = tid * per, b1 = min(NBK + 1, b0 + per);
+            int sum = 0;
+            for (int b = b0; b < b1; ++b) sum += bstart[b];
+            cursor[tid] = sum;
+            __syncthreads();
+            for (int off = 1; off < nt; off <<= 1) {
+                const int v = tid >= off ? cursor[tid - off] : 0;
+                __syncthreads();
+                cursor[tid] += v;
+                __syncthreads();
+            }
+            int run = tid > 0 ? cursor[tid - 1] : 0;
+            for (int b = b0; b < b1; ++b) {
+                run += bstart[b];
+                bstart[b] = run;
             }
         }
+        __syncthreads();
+        for (int b = tid; b < NBK; b += blockDim.x) cursor[b] = bstart[b];
+        __syncthreads();
+        for (int e = tid; e < n; e += blockDim.x) order[atomicAdd(&cursor[code[e] & 0xffff], 1)] = e;
+        __syncthreads();
+        // ---- C: each owner thread gathers the entries covering its line
+        if (owner) {
+            // the W buckets of one q0 along axis 1 are consecutive, so their
+            // entries form one contiguous run of the sorted order; the axis-1
+            // tap of an entry follows from its bucket coordinate b1
+            auto gather = [&](int idx, int t0) {
+                float wA = wl[t0 * E + idx];
+                if (D == 3) wA *= wl[(W + j1 + W - 1 - (code[idx] >> 16)) * E + idx];
+                const float2* up = uu + (cg * CG) * E + idx;
+                float2 uv[CG];
+#pragma unroll
+                for (int c = 0; c < CG; ++c) uv[c] = up[c * E];
+#pragma unroll
+                for (int z = 0; z < kZMax; ++z) {
+                    const float wt = wA * wz[z * E + idx];
+#pragma unroll
+                    for (int c = 0; c < CG; ++c) {
+                        acc[z][c].x = fmaf(wt, uv[c].x, acc[z][c].x);
+                        acc[z][c].y = fmaf(wt, uv[c].y, acc[z][c].y);
+                    }
+                }
+            };
+            for (int q0 = 0; q0 < W; ++q0) {
+                const int bb = D == 3 ? (j0 + q0) * NB1 + j1 : (j0 + q0);
+                const int e0 = bstart[bb], e1 = bstart[bb + (D == 3 ? W : 1)];
+                const int t0 = W - 1 - q0;
+                int e = e0;
+                for (; e + 1 < e1; e += 2) {
+                    const int i0 = order[e], i1 = order[e + 1];
+                    gather(i0, t0);
+                    gather(i1, t0);
+                }
+                if (e < e1) gather(order[e], t0);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
-    // write the tile back: plain stores for an owned tile, atomics for a split one
-    for (int i = threadIdx.x; i < Bt * C; i += blockDim.x) {
-        const int l = i / C, c = i % C;
-        int64_t gidx;
-        if (D == 2) {
-            const int l0 = l / a.B[1], l1 = l % a.B[1];
-            gidx = (int64_t)(tc[0] * a.B[0] + l0) * a.G[1] + (tc[1] * a.B[1] + l1);
-        } else {
-            const int l2 = l % a.B[2];
-            const int l01 = l / a.B[2];
-            const int l1 = l01 % a.B[1], l0 = l01 / a.B[1];
-            gidx = ((int64_t)(tc[0] * a.B[0] + l0) * a.G[1] + (tc[1] * a.B[1] + l1)) * a.G[2] +
-                   (tc[2] * a.B[2] + l2);
-        }
-        float2* dst = a.grid + gidx * C + c;
-        if (atomic) {
-            unsafeAtomicAdd(&dst->x, re[i]);
-            unsafeAtomicAdd(&dst->y, im[i]);
-        } else {
-            *dst = make_float2(re[i], im[i]);
+    // ---- D: write the owned lines back
+    if (owner) {
+        int64_t row;
+        if (D == 3)
+            row = ((int64_t)(org[0] + j0) * a.G[1] + (org[1] + j1)) * a.G[2] + org[2];
+        else
+            row = (int64_t)(org[0] + j0) * a.G[1] + org[1];
+#pragma unroll
+        for (int z = 0; z < kZMax; ++z) {
+            if (z >= ZL) break;
+            float2* dst = a.grid + (row + z) * C + cg * CG;
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                if (atomic) {
+                    unsafeAtomicAdd(&dst[c].x, acc[z][c].x);
+                    unsafeAtomicAdd(&dst[c].y, acc[z][c].y);
+                } else {
+                    dst[c] = acc[z][c];
+                }
+            }
         }
     }
 }
 
-void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, int lds_bytes,
-                   hipStream_t s) {
-    if (a.nwork <= 0) return;
-    const dim3 grid((unsigned)a.nwork), block(256);
-#define KP_SPREAD_W(DD, WW)                                                              \
-    if (d == DD && W == WW) {                                                            \
-        hipLaunchKernelGGL((k_spread<DD, WW>), grid, block, lds_bytes, s, a, kb);        \
-        KP_LAUNCH_CHECK();                                                               \
-        return;                                                                          \
+template <int D, int W>
+static void spread_dispatch(const SpreadArgs& a, const KbParams& kb, hipStream_t s) {
+    const int CG = coil_group(a.C);
+    const size_t lds = spread_lds_bytes(D, W, a.B, a.C);
+    const int nthr = spread_threads(D, a.B, a.C);
+    const int block = ((nthr + 63) / 64) * 64;
+    if (block > 256) fail(KP_ERR_UNSUPPORTED, "spreading tile needs more than 256 threads");
+    const dim3 grid((unsigned)a.nwork);
+    if (CG == 4) {
+        (void)hipFuncSetAttribute((const void*)k_spread<D, W, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_spread<D, W, 4>), grid, dim3(block), lds, s, a, kb);
+    } else if (CG == 2) {
+        (void)hipFuncSetAttribute((const void*)k_spread<D, W, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_spread<D, W, 2>), grid, dim3(block), lds, s, a, kb);
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_spread<D, W, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_spread<D, W, 1>), grid, dim3(block), lds, s, a, kb);
     }
+    KP_LAUNCH_CHECK();
+}
+
+void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, hipStream_t s) {
+    if (a.nwork <= 0) return;
+#define KP_SPREAD_W(DD, WW) \
+    if (d == DD && W == WW) return spread_dispatch<DD, WW>(a, kb, s);
     KP_SPREAD_W(2, 2) KP_SPREAD_W(2, 4) KP_SPREAD_W(2, 6) KP_SPREAD_W(2, 8)
     KP_SPREAD_W(3, 2) KP_SPREAD_W(3, 4) KP_SPREAD_W(3, 6) KP_SPREAD_W(3, 8)
 #undef KP_SPREAD_W

@@ -106,12 +106,15 @@ void fft_factor(int L, int* nst, int* rad);
 size_t fft_lds_bytes(int L, int ncol);
 
 // ------------------------------------------------------------ gridding
+// Kaiser-Bessel weights of the W taps of a sample as polynomials in
+// x = frac(g) - 1/2: weight of tap t = sum_k poly[t][k] x^k (degree 9,
+// fitted on the host in double precision at Chebyshev nodes).
+constexpr int kPolyN = 10;
 struct KbParams {
-    float beta2_4;   // beta^2 / 4
-    float inv_half;  // 2 / W
-    float inv_w;     // 1 / W
-    int nterms;      // series terms of I0
+    float poly[8][kPolyN];
 };
+void kb_fit(double beta, int W, KbParams* kb);
+double kb_kernel_host(double u, int W, double beta);
 
 enum InterpOut { IO_CALLER = 0, IO_INTERNAL = 1, IO_DUAL = 2, IO_PMUL = 3 };
 
@@ -145,10 +148,14 @@ struct SpreadArgs {
     int nb[3];
 };
 
+// spreading launch geometry derived from the tile shape
+constexpr int kSpreadChunk = 256;   // touch entries staged in LDS at a time
+constexpr int kZMax = 8;            // tile extent along the last axis (max)
+int spread_threads(int d, const int* B, int C);
+size_t spread_lds_bytes(int d, int W, const int* B, int C);
+
 void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStream_t s);
-void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, int lds_bytes,
-                   hipStream_t s);
-void upload_kb_constants();
+void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, hipStream_t s);
 
 // ------------------------------------------------------------ plan
 struct Plan {
@@ -235,7 +242,6 @@ void permute_p_to_internal(const float* p_caller, float* pint, const int32_t* pe
 void permute_p_to_caller(const float* pint, float* p_caller, const int32_t* perm, int64_t M,
                          int C, bool mc, hipStream_t s);
 
-int nterms_for(double beta2_4);
 
 // solver helpers (solver.hip)
 void fill2(float2* x, int64_t n, float re, float im, hipStream_t s);

@@ -404,7 +404,6 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
                   const void* maps, float oversamp, int kb_width, const kp_tuning* tuning, hipStream_t s,
                   bool channel_mode) {
     validate_plan_args(ndim, shape, ncoils, nsamples, coords, maps, oversamp, kb_width, tuning, channel_mode);
-    upload_kb_constants();
     auto P = std::make_unique<Plan>();
     P->d = ndim;
     P->C = ncoils;
@@ -422,10 +421,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     }
     const double a = (double)oversamp, w = (double)kb_width;
     P->beta = M_PI * std::sqrt((w / a) * (w / a) * (a - 0.5) * (a - 0.5) - 0.8);
-    P->kb.beta2_4 = (float)(P->beta * P->beta / 4.0);
-    P->kb.inv_half = (float)(2.0 / w);
-    P->kb.inv_w = (float)(1.0 / w);
-    P->kb.nterms = nterms_for(P->beta * P->beta / 4.0);
+    kb_fit(P->beta, kb_width, &P->kb);
 
     int dev = 0;
     KP_HIP(hipGetDevice(&dev));
@@ -433,23 +429,36 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_HIP(hipGetDeviceProperties(&prop, dev));
     P->lds_max = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
 
-    // tiles: about 48 KB of LDS accumulator (C floats x 2 per cell)
+    // tiles: the last axis at most kZMax cells (one register line per owner
+    // thread); 3D leading axes 8 x 8, 2D leading axis up to 64 lines, within
+    // 256 threads; every B_a divides G_a and leaves G_a >= B_a + W - 1.
     const int C = (int)ncoils;
-    const double cells = 49152.0 / (8.0 * C);
-    const int target = (int)std::floor(std::pow(cells, 1.0 / ndim) + 1e-9);
+    const int CG = C % 4 == 0 ? 4 : (C % 2 == 0 ? 2 : 1);
+    const int ncg = C / CG;
     for (int ax = 0; ax < 3; ++ax) {
         if (ax >= ndim) {
             P->B[ax] = 1;
             P->nb[ax] = 1;
             continue;
         }
-        int b = (tuning && tuning->bin_size[ax] > 0) ? tuning->bin_size[ax] : pick_bin(P->G[ax], std::max(target, 1));
+        const int cap = std::max(1, P->G[ax] - kb_width + 1);
+        int target;
+        if (ax == ndim - 1)
+            target = kZMax;
+        else if (ndim == 3)
+            target = 8;
+        else
+            target = std::max(1, std::min(64, 256 / ncg));
+        int b = (tuning && tuning->bin_size[ax] > 0) ? tuning->bin_size[ax] : pick_bin(P->G[ax], std::min(target, cap));
+        if (b > cap) fail(KP_ERR_INVALID_ARG, "tuning.bin_size must leave G_a >= bin + W - 1");
+        if (ax == ndim - 1 && b > kZMax) fail(KP_ERR_INVALID_ARG, "tuning.bin_size on the last axis must be <= 8");
         P->B[ax] = b;
         P->nb[ax] = P->G[ax] / b;
     }
     P->nbins = (int64_t)P->nb[0] * P->nb[1] * P->nb[2];
-    P->spread_lds = (int)(8 * (int64_t)P->B[0] * P->B[1] * P->B[2] * C);
-    if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading tile does not fit in LDS");
+    if (spread_threads(ndim, P->B, C) > 256) fail(KP_ERR_INVALID_ARG, "tuning.bin_size gives more than 256 threads");
+    P->spread_lds = (int)spread_lds_bytes(ndim, kb_width, P->B, C);
+    if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading chunk does not fit in LDS");
     if (P->nbins >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");
     const int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 2048;
 
@@ -757,8 +766,7 @@ float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
         a.B[ax] = P.B[ax];
         a.nb[ax] = P.nb[ax];
     }
-    const int lds = (int)(8 * (int64_t)P.B[0] * P.B[1] * P.B[2] * C);
-    launch_spread(P.d, P.W, a, P.kb, lds, s);
+    launch_spread(P.d, P.W, a, P.kb, s);
     return grid;
 }
 

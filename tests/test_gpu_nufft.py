@@ -50,6 +50,10 @@ CASES = [
     ((16, 20, 24), 2, 4000, 1.25, 4),
     ((12, 10, 8), 4, 1000, 2.0, 2),
     ((24, 24), 8, 2049, 1.25, 8),
+    # grids of the specialised FFT lengths (160, 200, 256, 400)
+    ((160, 128), 8, 20000, 1.25, 4),
+    ((128, 200), 1, 20000, 2.0, 4),
+    ((128, 128, 160), 2, 30000, 1.25, 4),
 ]
 
 
