@@ -317,7 +317,7 @@ __device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restric
         const int j = tid / NC + k * (256 / NC);
         if (k * 256 + tid < TOT) {
 #pragma unroll
-            for (int t = 0; t < R; ++t) v[k][t] = buf[(j + t * NBF) * NC + col];
+            for (int t = 0; t < R; ++t) v[k][t] = buf[(j + t * NBF) * (NC + 1) + col];
         }
     }
     __syncthreads();
@@ -337,7 +337,7 @@ __device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restric
             dft_c<R>(v[k], inv);
             const int base = (j / NS) * NS * R + kk;
 #pragma unroll
-            for (int t = 0; t < R; ++t) buf[(base + t * NS) * NC + col] = v[k][t];
+            for (int t = 0; t < R; ++t) buf[(base + t * NS) * (NC + 1) + col] = v[k][t];
         }
     }
     __syncthreads();
@@ -347,6 +347,7 @@ template <int L, int NC>
 __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
     extern __shared__ float2 buf[];
     constexpr int RS = 256 / NC;  // rows per sweep of the block
+    constexpr int LS = NC + 1;    // LDS row stride (padded against bank conflicts)
     const int tid = threadIdx.x;
     const int col = tid % NC, rb = tid / NC;
     const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
@@ -360,7 +361,7 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
     // ---- load (pruned)
     if (p.pad_in) {
         const int g0 = p.Lin / 2, g1 = L - p.Lin + p.Lin / 2;
-        for (int q = g0 + rb; q < g1; q += RS) buf[q * NC + col] = make_float2(0.f, 0.f);
+        for (int q = g0 + rb; q < g1; q += RS) buf[q * LS + col] = make_float2(0.f, 0.f);
     }
     for (int r = rb; r < p.Lin; r += RS) {
         float2 v = make_float2(0.f, 0.f);
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
             pos = r - p.Lin / 2;
             pos += pos < 0 ? L : 0;
         }
-        buf[pos * NC + col] = v;
+        buf[pos * LS + col] = v;
     }
     __syncthreads();
 
@@ -406,7 +407,7 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
             }
             const int64_t e = oo * p.Lout + m;
             const float2* mp = p.qmaps + e * C;
-            const float2* row = buf + q * NC + ol * C;
+            const float2* row = buf + q * LS + ol * C;
             float2 acc = make_float2(0.f, 0.f);
             for (int c = 0; c < C; ++c) acc = cadd(acc, cmulc(row[c], mp[c]));
             acc = cscale(acc, p.fo[oo] * p.fr[m]);
@@ -434,7 +435,7 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
             q = m - p.Lout / 2;
             q += q < 0 ? L : 0;
         }
-        const float2 v = buf[q * NC + col];
+        const float2 v = buf[q * LS + col];
         if (p.post == POST_NONE) {
             p.out[o * p.out_os + m * p.out_rs + i] = v;
         } else {
@@ -468,7 +469,7 @@ static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     if (p.post == POST_MAPS && (256 % p.Ob) != 0) return false;
     fft_kernel_t fn = nc == 16 ? fixed_for<16>(p.L) : fixed_for<8>(p.L);
     if (!fn) return false;
-    const size_t lds = sizeof(float2) * (size_t)p.L * nc;
+    const size_t lds = sizeof(float2) * (size_t)p.L * (nc + 1);
     if (lds > (size_t)lim) return false;
     if (lds > 65536) {
         (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);

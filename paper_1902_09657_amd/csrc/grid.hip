@@ -107,6 +107,16 @@ __device__ __forceinline__ void axis_taps(float g, int Ga, const KbParams& kb, f
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs of the chip round-robin (block p
+// runs on XCD p mod 8).  Remapping p so that each XCD takes one contiguous
+// eighth of the logical blocks keeps neighbouring tiles, whose footprints
+// share grid cells, in the same XCD's L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned nblk) {
+    const unsigned nx = 8, q = nblk / nx, r = nblk % nx;
+    const unsigned x = p % nx, k = p / nx;
+    return x * q + min(x, r) + k;
+}
+
 // ------------------------------------------------------------ interpolation
 // One thread per (sorted sample, group of CH coils), coil group fastest, so
 // the lanes of one sample read one contiguous C-vector per tap.
@@ -253,7 +263,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
     int* cursor = bstart + NBK + 1;
 
     const int4 wk = a.work[blockIdx.x];
-    const int tile = wk.x, start = wk.y, count = wk.z, atomic = wk.w;
+    const int tile = wk.x, start = wk.y, count = wk.z, slot = wk.w;
     int tc[3] = {0, 0, 0};
     {
         int rem = tile;
@@ -392,21 +402,72 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
             row = ((int64_t)(org[0] + j0) * a.G[1] + (org[1] + j1)) * a.G[2] + org[2];
         else
             row = (int64_t)(org[0] + j0) * a.G[1] + org[1];
+        // a split tile writes its partial sums to its own slot; the slots of
+        // a tile are added in order afterwards (k_reduce_partials)
+        const int64_t cells = (int64_t)B0 * B1 * ZL;
+        float2* base = slot < 0 ? a.grid + row * C : a.partial + ((int64_t)slot * cells + (int64_t)line * ZL) * C;
 #pragma unroll
         for (int z = 0; z < kZMax; ++z) {
             if (z >= ZL) break;
-            float2* dst = a.grid + (row + z) * C + cg * CG;
+            float2* dst = base + (int64_t)z * C + cg * CG;
 #pragma unroll
-            for (int c = 0; c < CG; ++c) {
-                if (atomic) {
-                    unsafeAtomicAdd(&dst[c].x, acc[z][c].x);
-                    unsafeAtomicAdd(&dst[c].y, acc[z][c].y);
-                } else {
-                    dst[c] = acc[z][c];
-                }
-            }
+            for (int c = 0; c < CG; ++c) dst[c] = acc[z][c];
         }
     }
+}
+
+// Sum the partial tiles of every split tile in slot order into the grid.
+// heavy[h] = (tile, first slot, number of slots).
+__global__ void k_reduce_partials(SpreadArgs a, const int4* heavy, int d) {
+    const int4 h = heavy[blockIdx.x];
+    const int B0 = a.B[0], B1 = d == 3 ? a.B[1] : 1, ZL = a.B[d - 1];
+    const int C = a.C;
+    const int64_t cells = (int64_t)B0 * B1 * ZL;
+    int tc[3] = {0, 0, 0}, rem = h.x;
+    for (int ax = d - 1; ax >= 0; --ax) {
+        tc[ax] = rem % a.nb[ax];
+        rem /= a.nb[ax];
+    }
+    const int64_t i = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (i < cells * C) {
+        // slots summed in order, four independent loads in flight
+        const float2* src = a.partial + (int64_t)h.y * cells * C + i;
+        const int64_t st = cells * C;
+        float2 s = make_float2(0.f, 0.f);
+        int q = 0;
+        for (; q + 4 <= h.z; q += 4) {
+            const float2 v0 = src[(q + 0) * st], v1 = src[(q + 1) * st];
+            const float2 v2 = src[(q + 2) * st], v3 = src[(q + 3) * st];
+            s.x += v0.x; s.y += v0.y;
+            s.x += v1.x; s.y += v1.y;
+            s.x += v2.x; s.y += v2.y;
+            s.x += v3.x; s.y += v3.y;
+        }
+        for (; q < h.z; ++q) {
+            const float2 v = src[q * st];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        const int64_t cell = i / C;
+        const int c = (int)(i % C);
+        const int z = (int)(cell % ZL);
+        const int64_t line = cell / ZL;
+        int64_t row;
+        if (d == 3) {
+            const int j0 = (int)(line / B1), j1 = (int)(line % B1);
+            row = ((int64_t)(tc[0] * B0 + j0) * a.G[1] + (tc[1] * B1 + j1)) * a.G[2] + tc[2] * ZL;
+        } else {
+            row = (int64_t)(tc[0] * B0 + line) * a.G[1] + tc[1] * ZL;
+        }
+        a.grid[(row + z) * C + c] = s;
+    }
+}
+
+void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, int d, hipStream_t s) {
+    if (nheavy <= 0) return;
+    const int64_t n = (int64_t)a.B[0] * (d == 3 ? a.B[1] : 1) * a.B[d - 1] * a.C;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nheavy, (unsigned)((n + 255) / 256)), dim3(256), 0, s, a, heavy, d);
+    KP_LAUNCH_CHECK();
 }
 
 template <int D, int W>

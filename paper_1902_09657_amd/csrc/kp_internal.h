@@ -140,8 +140,9 @@ struct SpreadArgs {
     const float* g;           // sorted coords [M][d]
     const float2* k;          // internal k-space [M][C]
     const int32_t* touch;     // entries (sorted sample positions)
-    const int4* work;         // (tile, start, count, atomic)
+    const int4* work;         // (tile, start, count, partial slot or -1)
     int64_t nwork;
+    float2* partial;          // [slots][tile cells][C] partial tiles of split tiles
     int C;
     int G[3];
     int B[3];
@@ -149,13 +150,14 @@ struct SpreadArgs {
 };
 
 // spreading launch geometry derived from the tile shape
-constexpr int kSpreadChunk = 256;   // touch entries staged in LDS at a time
+constexpr int kSpreadChunk = 128;   // touch entries staged in LDS at a time
 constexpr int kZMax = 8;            // tile extent along the last axis (max)
 int spread_threads(int d, const int* B, int C);
 size_t spread_lds_bytes(int d, int W, const int* B, int C);
 
 void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStream_t s);
 void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, hipStream_t s);
+void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, int d, hipStream_t s);
 
 // ------------------------------------------------------------ plan
 struct Plan {
@@ -183,6 +185,8 @@ struct Plan {
 
     DevBuf coords;                // caller's coordinates [M][d]
     DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
+    DevBuf partial;               // partial tiles of split tiles
+    int64_t nslots = 0;
     DevBuf maps;                  // [N][C]
     DevBuf fo_fwd, fr_fwd;        // deapodisation factors for the first/last pass
     DevBuf tw[3];                 // twiddles per axis

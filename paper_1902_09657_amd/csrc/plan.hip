@@ -460,7 +460,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     P->spread_lds = (int)spread_lds_bytes(ndim, kb_width, P->B, C);
     if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading chunk does not fit in LDS");
     if (P->nbins >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");
-    const int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 2048;
+    const int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 1024;
 
     const int64_t M = nsamples;
     const int d = ndim;
@@ -527,15 +527,23 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     std::vector<int> toff(P->nbins + 1);
     KP_HIP(hipMemcpyAsync(toff.data(), P->touch_off.p, sizeof(int) * (P->nbins + 1), hipMemcpyDeviceToHost, s));
     KP_HIP(hipStreamSynchronize(s));
+    // A tile with more entries than max_chunk is split; each piece gets a
+    // partial-tile slot.  Work items run longest first (split pieces, then
+    // owned tiles by decreasing entry count): the density of a radial
+    // trajectory is concentrated in a few tiles, and this order keeps every
+    // compute unit busy to the end.
     std::vector<int4> heavy_items, light_items;
-    std::vector<int> heavy;
+    std::vector<int4> heavy;  // (tile, first slot, slots, 0)
+    int nslots = 0;
     for (int64_t t = 0; t < P->nbins; ++t) {
         const int o = toff[t], n = toff[t + 1] - toff[t];
         if (n <= max_chunk) {
-            light_items.push_back(make_int4((int)t, o, n, 0));
+            light_items.push_back(make_int4((int)t, o, n, -1));
         } else {
-            heavy.push_back((int)t);
-            for (int q = 0; q < n; q += max_chunk) heavy_items.push_back(make_int4((int)t, o + q, std::min(max_chunk, n - q), 1));
+            const int first = nslots;
+            for (int q = 0; q < n; q += max_chunk)
+                heavy_items.push_back(make_int4((int)t, o + q, std::min(max_chunk, n - q), nslots++));
+            heavy.push_back(make_int4((int)t, first, nslots - first, 0));
         }
     }
     std::stable_sort(light_items.begin(), light_items.end(), [](const int4& x, const int4& y) { return x.z > y.z; });
@@ -543,11 +551,13 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     items.insert(items.end(), light_items.begin(), light_items.end());
     P->nwork = (int64_t)items.size();
     P->heavy_tiles = (int64_t)heavy.size();
+    P->nslots = nslots;
     P->work.alloc(sizeof(int4) * items.size());
     KP_HIP(hipMemcpy(P->work.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice));
-    P->heavy_list.alloc(sizeof(int) * std::max<size_t>(heavy.size(), 1));
+    P->heavy_list.alloc(sizeof(int4) * std::max<size_t>(heavy.size(), 1));
     if (!heavy.empty())
-        KP_HIP(hipMemcpy(P->heavy_list.p, heavy.data(), sizeof(int) * heavy.size(), hipMemcpyHostToDevice));
+        KP_HIP(hipMemcpy(P->heavy_list.p, heavy.data(), sizeof(int4) * heavy.size(), hipMemcpyHostToDevice));
+    P->partial.alloc(sizeof(float2) * std::max<int64_t>(1, (int64_t)nslots * P->B[0] * P->B[1] * P->B[2] * C));
 
     // ---- coil maps, stored [N][C]; unit maps for a single coil without maps
     P->has_maps = maps != nullptr;
@@ -611,7 +621,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_HIP(hipStreamSynchronize(s));
 
     int64_t total = 0;
-    for (DevBuf* b : {&P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->touch_off, &P->touch, &P->work,
+    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->touch_off, &P->touch, &P->work,
                       &P->heavy_list, &P->maps, &P->fo_fwd, &P->fr_fwd, &P->bufA, &P->bufB, &P->kint, &P->kint2, &P->kint3,
                       &P->pint, &P->red, &P->sched})
         total += (int64_t)b->bytes;
@@ -747,12 +757,6 @@ void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStre
 
 float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
     float2* grid = P.bufA.as<float2>();
-    Geom gm = make_geom(P);
-    if (P.heavy_tiles > 0) {
-        hipLaunchKernelGGL(k_zero_tiles, dim3((unsigned)P.heavy_tiles), dim3(256), 0, s, grid,
-                           P.heavy_list.as<int>(), (int)P.heavy_tiles, P.d, gm, C);
-        KP_LAUNCH_CHECK();
-    }
     SpreadArgs a{};
     a.grid = grid;
     a.g = P.g_sorted.as<float>();
@@ -760,6 +764,7 @@ float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
     a.touch = P.touch.as<int32_t>();
     a.work = P.work.as<int4>();
     a.nwork = P.nwork;
+    a.partial = P.partial.as<float2>();
     a.C = C;
     for (int ax = 0; ax < 3; ++ax) {
         a.G[ax] = P.G[ax];
@@ -767,6 +772,7 @@ float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
         a.nb[ax] = P.nb[ax];
     }
     launch_spread(P.d, P.W, a, P.kb, s);
+    launch_reduce_partials(a, P.heavy_list.as<int4>(), (int)P.heavy_tiles, P.d, s);
     return grid;
 }
 
