@@ -1,0 +1,109 @@
+"""torch.autograd.Function wrappers over the library's differentiable calls.
+
+Gradient convention is PyTorch's for complex tensors (grad = dL/dRe + i dL/dIm),
+under which the vector-Jacobian product of a complex-linear map is its
+conjugate transpose: A's backward is A^H and A^H's backward is A.  Every
+computation (NUFFT, unrolled PDHG, its reverse recursion) runs in the HIP
+library; these classes only marshal tensors.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import _lib
+from . import Plan, nufft_adjoint, nufft_forward, _p_kind, _ptr, _stream, _dev
+
+
+class SenseNufft(torch.autograd.Function):
+    """y = A x (multi-coil SENSE NUFFT); backward applies A^H."""
+
+    @staticmethod
+    def forward(ctx, x, plan: Plan):
+        ctx.plan = plan
+        return nufft_forward(plan, x)
+
+    @staticmethod
+    def backward(ctx, gy):
+        return nufft_adjoint(ctx.plan, gy.contiguous()), None
+
+
+class SenseNufftAdjoint(torch.autograd.Function):
+    """x = A^H y; backward applies A."""
+
+    @staticmethod
+    def forward(ctx, y, plan: Plan):
+        ctx.plan = plan
+        return nufft_adjoint(plan, y)
+
+    @staticmethod
+    def backward(ctx, gx):
+        return nufft_forward(ctx.plan, gx.contiguous()), None
+
+
+def pack_params(sigma, tau, theta, lam):
+    """Learnable step sizes as one float32 vector [3K+1] (sigma, tau, theta, lambda)."""
+    return torch.cat([sigma.reshape(-1), tau.reshape(-1), theta.reshape(-1), lam.reshape(1)]).float().contiguous()
+
+
+class UnrolledPdhg(torch.autograd.Function):
+    """x_K of K unrolled l2 PDHG steps with learnable per-step sizes and lambda.
+
+    forward(y, params, plan, p, K, ckpt_every, x0=None) -> x_K
+      y      complex64 [C][M] data (differentiable)
+      params float32 [3K+1] = sigma[K], tau[K], theta[K], lambda (differentiable)
+      p      None, float32 [M] (single-channel) or [C][M] (multi-channel)
+      x0     None or complex64 image (differentiable)
+    Iterates are checkpointed every `ckpt_every` steps; the backward pass
+    recomputes each segment from its checkpoint.
+    """
+
+    @staticmethod
+    def forward(ctx, y, params, plan: Plan, p, K: int, ckpt_every: int, x0=None):
+        L = _lib.load()
+        y = _dev(y, torch.complex64, "y")
+        params = _dev(params, torch.float32, "params")
+        if params.numel() != 3 * K + 1:
+            raise ValueError("params must hold 3K+1 values")
+        if p is not None:
+            p = _dev(p, torch.float32, "p")
+        if x0 is not None:
+            x0 = _dev(x0, torch.complex64, "x0")
+        nbytes = L.pdhg_unrolled_ckpt_bytes(plan.handle, int(K), int(ckpt_every))
+        if nbytes <= 0:
+            raise ValueError("invalid K / ckpt_every")
+        ckpt = torch.empty(nbytes, dtype=torch.uint8, device=y.device)
+        x = torch.empty(plan.shape, dtype=torch.complex64, device=y.device)
+        _lib.check(L.pdhg_unrolled_forward(plan.handle, _ptr(y), _ptr(p), _p_kind(p), _ptr(params), int(K),
+                                           int(ckpt_every), _ptr(x0), _ptr(x), _ptr(ckpt), _stream()))
+        ctx.plan, ctx.K, ctx.S = plan, int(K), int(ckpt_every)
+        ctx.has_p = p is not None
+        ctx.has_x0 = x0 is not None
+        extra = ([p] if p is not None else []) + ([x0] if x0 is not None else [])
+        ctx.save_for_backward(y, params, ckpt, *extra)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        L = _lib.load()
+        saved = list(ctx.saved_tensors)
+        y, params, ckpt = saved[:3]
+        rest = saved[3:]
+        p = rest.pop(0) if ctx.has_p else None
+        x0 = rest.pop(0) if ctx.has_x0 else None
+        gx = gx.contiguous().to(torch.complex64)
+        g_params = torch.empty_like(params)
+        g_y = torch.empty_like(y)
+        g_x0 = torch.empty(ctx.plan.shape, dtype=torch.complex64, device=y.device) if ctx.has_x0 else None
+        _lib.check(L.pdhg_unrolled_backward(ctx.plan.handle, _ptr(y), _ptr(p), _p_kind(p), _ptr(params), ctx.K, ctx.S,
+                                            _ptr(x0), _ptr(ckpt), _ptr(gx), _ptr(g_params), _ptr(g_y), _ptr(g_x0),
+                                            _stream()))
+        return g_y, g_params, None, None, None, None, g_x0
+
+
+def unrolled_pdhg(y, params, plan, p=None, K=10, ckpt_every=None, x0=None):
+    """Functional form of UnrolledPdhg; ckpt_every defaults to ceil(sqrt(K))."""
+    if ckpt_every is None:
+        ckpt_every = max(1, math.ceil(math.sqrt(K)))
+    return UnrolledPdhg.apply(y, params, plan, p, int(K), int(ckpt_every), x0)

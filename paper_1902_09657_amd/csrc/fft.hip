@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_fft_pass(FftPass p) {
             } else if (p.epi == EPI_L2) {
                 const float tau = *p.e_tau, th = *p.e_theta;
                 const float2 xo = p.ex[e];
-                const float den = 1.f / (1.f + tau * p.e_lambda);
+                const float den = 1.f / (1.f + tau * (p.e_lam ? *p.e_lam : p.e_lambda));
                 const float2 xn = make_float2((xo.x - tau * acc.x) * den, (xo.y - tau * acc.y) * den);
                 p.exbar[e] = make_float2(xn.x + th * (xn.x - xo.x), xn.y + th * (xn.y - xo.y));
                 p.ex[e] = xn;
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
             } else if (p.epi == EPI_L2) {
                 const float tau = *p.e_tau, th = *p.e_theta;
                 const float2 xo = p.ex[e];
-                const float den = 1.f / (1.f + tau * p.e_lambda);
+                const float den = 1.f / (1.f + tau * (p.e_lam ? *p.e_lam : p.e_lambda));
                 const float2 xn = make_float2((xo.x - tau * acc.x) * den, (xo.y - tau * acc.y) * den);
                 p.exbar[e] = make_float2(xn.x + th * (xn.x - xo.x), xn.y + th * (xn.y - xo.y));
                 p.ex[e] = xn;

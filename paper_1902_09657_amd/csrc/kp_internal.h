@@ -99,6 +99,7 @@ struct FftPass {
     const float* e_tau;            // device scalars
     const float* e_theta;
     float e_lambda;
+    const float* e_lam;            // device lambda (overrides e_lambda when set)
 };
 
 void launch_fft_pass(const FftPass& p, hipStream_t s);
@@ -230,6 +231,7 @@ struct AdjOpts {
     const float* tau = nullptr;
     const float* theta = nullptr;
     float lambda = 0.f;
+    const float* lam = nullptr;      // device lambda (overrides `lambda`)
 };
 // Inverse FFT passes + post-pass from grid (in bufA) to image `out`
 void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStream_t s);

@@ -739,6 +739,7 @@ void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStre
             fp.e_tau = o.tau;
             fp.e_theta = o.theta;
             fp.e_lambda = o.lambda;
+            fp.e_lam = o.lam;
             if (!o.channel) {
                 fp.Ib = C;
                 fp.Ob = std::max(1, 16 / C);

@@ -1,0 +1,93 @@
+"""GPU parity of the differentiable form: autograd over the SENSE-NUFFT and the
+unrolled l2 PDHG with checkpointing, against the FP64 oracle's reverse
+recursion (itself pinned to finite differences on the CPU)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import nufft as onufft
+from oracle import pdhg as opdhg
+from oracle import precond as oprecond
+from oracle import unrolled as ounrolled
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def setup(shape=(32, 40), C=3, M=2400, seed=0):
+    import paper_1902_09657_amd as kp
+    rng = np.random.default_rng(seed)
+    k = synth.spiral_2d(12, M // 12, 3.0)
+    maps = synth.coil_maps(shape, C, rng)
+    x = synth.phantom(shape, rng)
+    op = onufft.Nufft(k, shape, maps, 1.25, 4)
+    y = op.forward(x) + synth.noise((C, k.shape[0]), 1e-3, rng)
+    plan = kp.nufft_plan(dev(k, torch.float32), shape, dev(maps, torch.complex64), oversamp=1.25, kb_width=4)
+    return kp, plan, op, k, maps, x, y
+
+
+def test_sense_nufft_autograd():
+    from paper_1902_09657_amd.autograd import SenseNufft, SenseNufftAdjoint
+    kp, plan, op, k, maps, x, y = setup()
+    # a target unrelated to x keeps the residual O(1) (no cancellation)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)
+    xt = dev(x, torch.complex64).requires_grad_(True)
+    yt = dev(b, torch.complex64)
+    r = SenseNufft.apply(xt, plan) - yt
+    loss = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+    loss.backward()
+    want = op.adjoint(op.forward(x) - b)               # A^H (A x - b)
+    assert rel(xt.grad.cpu().numpy(), want) < 1e-4
+    yt2 = dev(y, torch.complex64).requires_grad_(True)
+    z = SenseNufftAdjoint.apply(yt2, plan)
+    loss2 = 0.5 * (z.real ** 2 + z.imag ** 2).sum()
+    loss2.backward()
+    assert rel(yt2.grad.cpu().numpy(), op.forward(op.adjoint(y))) < 1e-4
+    plan.close()
+
+
+@pytest.mark.parametrize("S", [1, 3, 6])
+def test_unrolled_pdhg_forward_and_gradients(S):
+    from paper_1902_09657_amd.autograd import UnrolledPdhg, pack_params
+    kp, plan, op, k, maps, x, y = setup(seed=1)
+    print("ckpt_every", S, flush=True)
+    shape = op.shape
+    K = 6
+    p = oprecond.efficient_nufft(maps, k, shape, 1.25, 4)
+    lmax = opdhg.power_method(op.forward, op.adjoint, p, shape, 30)
+    sig, tau, th = opdhg.schedule(lmax, float(p.min()), K)
+    lam = 1e-2
+    rng = np.random.default_rng(2)
+    sig = sig * (1 + 0.1 * rng.standard_normal(K))
+    tau = tau * (1 + 0.1 * rng.standard_normal(K))
+    x0 = 0.05 * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    # oracle
+    xK, rec = ounrolled.forward(op.forward, op.adjoint, y, p, sig, tau, th, lam, shape, x0=x0)
+    g = ounrolled.backward(op.forward, op.adjoint, y, p, sig, tau, th, lam, rec, xK - x)
+    # GPU
+    params = pack_params(dev(sig, torch.float32), dev(tau, torch.float32), dev(th, torch.float32),
+                         torch.tensor([lam], dtype=torch.float32, device="cuda")).requires_grad_(True)
+    yt = dev(y, torch.complex64).requires_grad_(True)
+    x0t = dev(x0, torch.complex64).requires_grad_(True)
+    xg = UnrolledPdhg.apply(yt, params, plan, dev(p, torch.float32), K, S, x0t)
+    assert rel(xg.detach().cpu().numpy(), xK) < 1e-4
+    r = xg - dev(x, torch.complex64)
+    loss = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+    loss.backward()
+    gp = params.grad.cpu().numpy()
+    want = np.concatenate([g["sigma"], g["tau"], g["theta"], [g["lam"]]])
+    assert rel(gp, want) < 1e-3, (gp, want)
+    assert rel(yt.grad.cpu().numpy(), g["y"]) < 1e-3
+    assert rel(x0t.grad.cpu().numpy(), g["x0"]) < 1e-3
+    plan.close()
