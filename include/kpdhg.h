@@ -38,6 +38,7 @@ extern "C" {
 #endif
 
 typedef struct kp_plan* kp_plan_t;
+typedef struct kp_batch* kp_batch_t;
 
 enum {
     KP_OK = 0,
@@ -209,6 +210,55 @@ int nufft_plan_validate(int ndim, const int64_t* shape, int64_t ncoils, int64_t 
  *   KP_STAGE_ADJ_FFT  pruned inverse FFT passes + post-pass (d kernels) */
 enum { KP_STAGE_FWD_FFT = 0, KP_STAGE_INTERP = 1, KP_STAGE_SPREAD = 2, KP_STAGE_ADJ_FFT = 3 };
 int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent 2D reconstructions (slices) with their own image sizes
+ * and trajectories, solved together: the paper treats every slice of its
+ * multi-slice experiments as its own problem (Experiments), so a batch is
+ * a set of independent instances of Eq. model with one coil count, one
+ * oversampling and one kernel width.
+ *
+ * Pick tile shapes by timing candidate tilings of the spreading and
+ * interpolation kernels on this problem (`best`, host struct).  Results are
+ * cached per (shape, coils, sample-count class, width, oversampling), so a
+ * second call for a similar slice returns at once.  Synchronises `stream`;
+ * allocates and frees trial plans. */
+int nufft_autotune(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples,
+                   const float* coords, const void* maps, float oversamp, int kb_width,
+                   kp_tuning* best, void* stream);
+
+/* Build one plan per slice (arguments as nufft_plan, per slice):
+ *   shapes    host int64 [nslices][2]
+ *   nsamples  host int64 [nslices]
+ *   coords    host array of nslices device pointers, float32 [M_i][2]
+ *   maps      host array of nslices device pointers c64 [C][N_i], or NULL
+ *             (then C must be 1)
+ *   tune      1: tile shapes from nufft_autotune per slice; 0: built-in
+ * When every slice is 2D with W = 4, C a multiple of 4 and FFT lengths the
+ * specialised FFT kernels cover, the solve runs each phase of an iteration
+ * as ONE launch over all slices (nufft_batch_info reports it); otherwise it
+ * runs slice after slice inside the same captured graph. */
+int nufft_plan_batch(kp_batch_t* out, int nslices, const int64_t* shapes, const int64_t* nsamples,
+                     int64_t ncoils, const float* const* coords, const void* const* maps,
+                     float oversamp, int kb_width, int tune, void* stream);
+
+/* Plan facts of one slice; *fast (may be NULL) = 1 when the one-launch-per-
+ * phase path is used. */
+int nufft_batch_info(kp_batch_t batch, int slice, kp_plan_info* info, int* fast);
+
+/* l2-regularised PDHG (as pdhg_solve with reg = KP_REG_L2, no x0, u0 or
+ * objective) on every slice: y, p and x_out are host arrays of nslices
+ * device pointers with the per-slice layouts of pdhg_solve (p may be NULL
+ * for KP_PRECOND_NONE).  Each slice gets its own lambda_max (power method
+ * unless opts->lambda_max > 0) and step schedule.  The K iterations are
+ * captured once into a HIP graph that later calls with the same iters,
+ * lambda and p_kind replay; the first call (or one that changes them)
+ * allocates the graph and its descriptor tables. */
+int pdhg_solve_batch(kp_batch_t batch, const void* const* y, const float* const* p, int p_kind,
+                     const kp_pdhg_opts* opts, void* const* x_out, void* stream);
+
+/* Release a batch after synchronising the device.  NULL is ignored. */
+void nufft_batch_destroy(kp_batch_t batch);
 
 /* Thread-local message of the last failure (valid until the next call). */
 const char* kp_last_error(void);

@@ -17,7 +17,8 @@ from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVE
 
 __all__ = [
     "Plan", "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
-    "pdhg_solve", "nufft_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
+    "pdhg_solve", "nufft_destroy", "nufft_autotune", "Batch", "nufft_plan_batch", "nufft_batch_info",
+    "pdhg_solve_batch", "nufft_batch_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
     "KP_REG_L2", "KP_REG_L1_WAVELET",
 ]
 
@@ -195,3 +196,116 @@ def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_leve
 
 def nufft_destroy(plan: Plan):
     plan.close()
+
+
+def nufft_autotune(coords, shape, maps=None, oversamp=1.25, kb_width=4) -> dict:
+    """Tile shape picked by timing candidate tilings (cached per problem class)."""
+    coords = _dev(coords, torch.float32, "coords")
+    shape = tuple(int(n) for n in shape)
+    d = len(shape)
+    C = 1
+    if maps is not None:
+        maps = _dev(maps, torch.complex64, "maps")
+        C = maps.shape[0]
+    best = Tuning()
+    shp = (ctypes.c_int64 * d)(*shape)
+    _lib.check(_lib.load().nufft_autotune(d, shp, C, coords.shape[0], _ptr(coords), _ptr(maps), float(oversamp),
+                                          int(kb_width), ctypes.byref(best), _stream()))
+    return {"bin_size": tuple(best.bin_size[:d]), "max_chunk": best.max_chunk}
+
+
+class Batch:
+    """Plans of many independent 2D slices (owns the library handle)."""
+
+    def __init__(self, handle, shapes, ncoils, nsamples, device, keep):
+        self.handle = handle
+        self.shapes = [tuple(s) for s in shapes]
+        self.ncoils = int(ncoils)
+        self.nsamples = [int(m) for m in nsamples]
+        self.device = device
+        self._keep = keep
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def close(self):
+        if self.handle:
+            _lib.load().nufft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[0 if t is None else t.data_ptr() for t in ts])
+
+
+def nufft_plan_batch(coords, shapes, maps=None, oversamp=1.25, kb_width=4, tune=True) -> Batch:
+    """coords: list of float32 [M_i, 2]; shapes: list of (N0, N1); maps: list of [C, N0, N1] or None."""
+    n = len(coords)
+    if len(shapes) != n or (maps is not None and len(maps) != n):
+        raise ValueError("coords, shapes and maps must have one entry per slice")
+    coords = [_dev(c, torch.float32, "coords") for c in coords]
+    shapes = [tuple(int(v) for v in s) for s in shapes]
+    for c, s in zip(coords, shapes):
+        if len(s) != 2 or c.dim() != 2 or c.shape[1] != 2:
+            raise ValueError("batched slices are 2D: coords [M, 2], shape (N0, N1)")
+    C = 1
+    if maps is not None:
+        maps = [_dev(m, torch.complex64, "maps") for m in maps]
+        C = maps[0].shape[0]
+        for m, s in zip(maps, shapes):
+            if m.shape[0] != C or tuple(m.shape[1:]) != s:
+                raise ValueError("maps must be [C, *shape] with one C for all slices")
+    shp = (ctypes.c_int64 * (2 * n))(*[v for s in shapes for v in s])
+    ms = (ctypes.c_int64 * n)(*[c.shape[0] for c in coords])
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().nufft_plan_batch(ctypes.byref(h), n, shp, ms, C, _ptr_array(coords),
+                                            _ptr_array(maps) if maps is not None else None, float(oversamp),
+                                            int(kb_width), 1 if tune else 0, _stream()))
+    return Batch(h, shapes, C, [c.shape[0] for c in coords], coords[0].device, (coords, maps))
+
+
+def nufft_batch_info(batch: Batch, slice_index: int) -> dict:
+    inf = PlanInfo()
+    fast = ctypes.c_int(0)
+    _lib.check(_lib.load().nufft_batch_info(batch.handle, int(slice_index), ctypes.byref(inf), ctypes.byref(fast)))
+    d = inf.ndim
+    return {
+        "shape": tuple(inf.shape[:d]), "grid": tuple(inf.grid[:d]), "bin_size": tuple(inf.bin_size[:d]),
+        "nwork": inf.nwork, "heavy_tiles": inf.heavy_tiles, "fast": bool(fast.value),
+    }
+
+
+def pdhg_solve_batch(batch: Batch, y, p=None, lam=1e-3, iters=20, lambda_max=0.0, power_iters=30, sigma0=1.0,
+                     accel=True):
+    """l2 PDHG on every slice; y: list of [C, M_i]; p: None or list of [M_i] / [C, M_i]."""
+    n = len(batch)
+    if len(y) != n or (p is not None and len(p) != n):
+        raise ValueError("y and p must have one entry per slice")
+    y = [_dev(t, torch.complex64, "y") for t in y]
+    kind = KP_PRECOND_NONE
+    if p is not None:
+        p = [_dev(t, torch.float32, "p") for t in p]
+        kind = _p_kind(p[0])
+    o = PdhgOpts()
+    o.reg = KP_REG_L2
+    o.lam = float(lam)
+    o.iters = int(iters)
+    o.wavelet_levels = 4
+    o.lambda_max = float(lambda_max)
+    o.power_iters = int(power_iters)
+    o.sigma0 = float(sigma0)
+    o.accel = 1 if accel else 0
+    xs = [torch.empty(s, dtype=torch.complex64, device=batch.device) for s in batch.shapes]
+    _lib.check(_lib.load().pdhg_solve_batch(batch.handle, _ptr_array(y), _ptr_array(p) if p is not None else None,
+                                            kind, ctypes.byref(o), _ptr_array(xs), _stream()))
+    return xs
+
+
+def nufft_batch_destroy(batch: Batch):
+    batch.close()

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkpdhg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["plan.hip", "fft.hip", "grid.hip", "solver.hip", "precond.hip", "unrolled.hip"]
+SOURCES = ["plan.hip", "fft.hip", "grid.hip", "solver.hip", "precond.hip", "unrolled.hip", "batch.hip"]
 
 
 def hipcc() -> str:
@@ -51,7 +51,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(len(srcs), 6)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(srcs), 7)) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

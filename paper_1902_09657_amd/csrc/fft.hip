@@ -301,21 +301,21 @@ __device__ __forceinline__ void dft_c(float2* v, int inv) {
     else dft8(v, inv);
 }
 
-template <int L, int NC, int S>
+template <int L, int NC, int S, int NT>
 __device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restrict__ tw, int inv, int tid) {
     constexpr int R = fft_radix_c(L, S);
     if (R == 1) return;
     constexpr int NS = fft_span_c(L, S);
     constexpr int NBF = L / R;
     constexpr int TOT = NBF * NC;
-    constexpr int NB = (TOT + 255) / 256;
+    constexpr int NB = (TOT + NT - 1) / NT;
     constexpr int STRIDE = L / (NS * R);
     const int col = tid % NC;
     float2 v[NB][R];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        const int j = tid / NC + k * (256 / NC);
-        if (k * 256 + tid < TOT) {
+        const int j = tid / NC + k * (NT / NC);
+        if (k * NT + tid < TOT) {
 #pragma unroll
             for (int t = 0; t < R; ++t) v[k][t] = buf[(j + t * NBF) * (NC + 1) + col];
         }
@@ -323,8 +323,8 @@ __device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restric
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        const int j = tid / NC + k * (256 / NC);
-        if (k * 256 + tid < TOT) {
+        const int j = tid / NC + k * (NT / NC);
+        if (k * NT + tid < TOT) {
             const int kk = j % NS;
             if (NS > 1) {
 #pragma unroll
@@ -343,15 +343,13 @@ __device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restric
     __syncthreads();
 }
 
-template <int L, int NC>
-__global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
-    extern __shared__ float2 buf[];
-    constexpr int RS = 256 / NC;  // rows per sweep of the block
+template <int L, int NC, int NT>
+__device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, float2* buf) {
+    constexpr int RS = NT / NC;   // rows per sweep of the block (NT threads)
     constexpr int LS = NC + 1;    // LDS row stride (padded against bank conflicts)
     const int tid = threadIdx.x;
     const int col = tid % NC, rb = tid / NC;
     const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
-    const int64_t bid = blockIdx.x;
     const int64_t o0 = (bid / nIb) * p.Ob;
     const int64_t i0 = (bid % nIb) * p.Ib;
     const int64_t o = o0 + col / p.Ib, i = i0 + col % p.Ib;
@@ -385,17 +383,17 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
     }
     __syncthreads();
 
-    fixed_stage<L, NC, 0>(buf, p.tw, p.inverse, tid);
-    fixed_stage<L, NC, 1>(buf, p.tw, p.inverse, tid);
-    fixed_stage<L, NC, 2>(buf, p.tw, p.inverse, tid);
-    fixed_stage<L, NC, 3>(buf, p.tw, p.inverse, tid);
-    fixed_stage<L, NC, 4>(buf, p.tw, p.inverse, tid);
-    fixed_stage<L, NC, 5>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 0, NT>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 1, NT>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 2, NT>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 3, NT>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 4, NT>(buf, p.tw, p.inverse, tid);
+    fixed_stage<L, NC, 5, NT>(buf, p.tw, p.inverse, tid);
 
     // ---- store (pruned)
     if (p.post == POST_MAPS) {
         const int C = p.Ib;
-        const int tpo = 256 / p.Ob;  // threads per outer
+        const int tpo = NT / p.Ob;  // threads per outer
         const int ol = tid / tpo;
         const int64_t oo = o0 + ol;
         if (ol >= p.Ob || oo >= p.O) return;
@@ -445,19 +443,86 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
     }
 }
 
+template <int L, int NC, int NT>
+__global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
+    extern __shared__ float2 buf[];
+    fft_fixed_body<L, NC, NT>(p, blockIdx.x, buf);
+}
+
+// Column blocks of the specialised kernels: NC columns over NT threads with
+// NT a multiple of NC (8 or 16 columns on 256 threads; 12 columns, one
+// 12-coil row, on 192 threads).
+static int fixed_threads(int nc) { return nc == 12 ? 192 : ((nc == 8 || nc == 16) ? 256 : 0); }
+
+// One launch over the passes of many independent transforms (the slices of a
+// batch): block b runs pass s with blk_start[s] <= b < blk_start[s+1].  All
+// passes of one launch share the column block (NC, NT).
+template <int NC, int NT>
+__global__ void __launch_bounds__(256) k_fft_batch(const FftPass* __restrict__ passes,
+                                                   const int64_t* __restrict__ blk_start, int n) {
+    extern __shared__ float2 buf[];
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {  // last s with blk_start[s] <= b
+        const int mid = (lo + hi + 1) / 2;
+        if (blk_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const FftPass p = passes[lo];
+    const int64_t bid = b - blk_start[lo];
+    switch (p.L) {
+        case 160: fft_fixed_body<160, NC, NT>(p, bid, buf); break;
+        case 200: fft_fixed_body<200, NC, NT>(p, bid, buf); break;
+        case 240: fft_fixed_body<240, NC, NT>(p, bid, buf); break;
+        case 256: fft_fixed_body<256, NC, NT>(p, bid, buf); break;
+        case 320: fft_fixed_body<320, NC, NT>(p, bid, buf); break;
+        case 400: fft_fixed_body<400, NC, NT>(p, bid, buf); break;
+        default: break;
+    }
+}
+
+static bool batch_length(int L) { return L == 160 || L == 200 || L == 240 || L == 256 || L == 320 || L == 400; }
+
+bool fft_batchable(const FftPass& p) {
+    const int nc = p.Ob * p.Ib;
+    const int nt = fixed_threads(nc);
+    if (nc != 16 && nc != 12) return false;
+    if (p.post == POST_MAPS && (nt % p.Ob) != 0) return false;
+    return batch_length(p.L);
+}
+
+int64_t fft_pass_blocks(const FftPass& p) {
+    return ((p.I + p.Ib - 1) / p.Ib) * ((p.O + p.Ob - 1) / p.Ob);
+}
+
+void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n, int64_t nblk, int maxL, int nc,
+                      hipStream_t s) {
+    if (nblk <= 0) return;
+    const size_t lds = sizeof(float2) * (size_t)maxL * (nc + 1);
+    const void* fn = nc == 12 ? (const void*)k_fft_batch<12, 192> : (const void*)k_fft_batch<16, 256>;
+    if (lds > 65536) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    if (nc == 12)
+        hipLaunchKernelGGL((k_fft_batch<12, 192>), dim3((unsigned)nblk), dim3(192), lds, s, d_passes, d_blk_start, n);
+    else
+        hipLaunchKernelGGL((k_fft_batch<16, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
+    KP_LAUNCH_CHECK();
+}
+
 typedef void (*fft_kernel_t)(FftPass);
 
-template <int NC>
+template <int NC, int NT>
 static fft_kernel_t fixed_for(int L) {
     switch (L) {
-        case 160: return k_fft_fixed<160, NC>;
-        case 200: return k_fft_fixed<200, NC>;
-        case 240: return k_fft_fixed<240, NC>;
-        case 256: return k_fft_fixed<256, NC>;
-        case 320: return k_fft_fixed<320, NC>;
-        case 400: return k_fft_fixed<400, NC>;
-        case 512: return k_fft_fixed<512, NC>;
-        case 640: return k_fft_fixed<640, NC>;
+        case 160: return k_fft_fixed<160, NC, NT>;
+        case 200: return k_fft_fixed<200, NC, NT>;
+        case 240: return k_fft_fixed<240, NC, NT>;
+        case 256: return k_fft_fixed<256, NC, NT>;
+        case 320: return k_fft_fixed<320, NC, NT>;
+        case 400: return k_fft_fixed<400, NC, NT>;
+        case 512: return k_fft_fixed<512, NC, NT>;
+        case 640: return k_fft_fixed<640, NC, NT>;
         default: return nullptr;
     }
 }
@@ -465,9 +530,10 @@ static fft_kernel_t fixed_for(int L) {
 // try the specialised kernel; false if this pass does not fit it
 static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     const int nc = p.Ob * p.Ib;
-    if (nc != 8 && nc != 16) return false;
-    if (p.post == POST_MAPS && (256 % p.Ob) != 0) return false;
-    fft_kernel_t fn = nc == 16 ? fixed_for<16>(p.L) : fixed_for<8>(p.L);
+    const int nt = fixed_threads(nc);
+    if (nt == 0) return false;
+    if (p.post == POST_MAPS && (nt % p.Ob) != 0) return false;
+    fft_kernel_t fn = nc == 16 ? fixed_for<16, 256>(p.L) : (nc == 8 ? fixed_for<8, 256>(p.L) : fixed_for<12, 192>(p.L));
     if (!fn) return false;
     const size_t lds = sizeof(float2) * (size_t)p.L * (nc + 1);
     if (lds > (size_t)lim) return false;
@@ -475,12 +541,10 @@ static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
         (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         (void)hipGetLastError();
     }
-    const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
-    const int64_t nOb = (p.O + p.Ob - 1) / p.Ob;
-    const int64_t nblk = nIb * nOb;
+    const int64_t nblk = fft_pass_blocks(p);
     if (nblk <= 0) return true;
     if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "FFT pass grid too large");
-    hipLaunchKernelGGL(fn, dim3((unsigned)nblk), dim3(256), lds, s, p);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nblk), dim3(nt), lds, s, p);
     KP_LAUNCH_CHECK();
     return true;
 }

@@ -121,9 +121,8 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned nblk) {
 // One thread per (sorted sample, group of CH coils), coil group fastest, so
 // the lanes of one sample read one contiguous C-vector per tap.
 template <int D, int W, int CH>
-__global__ void __launch_bounds__(256) k_interp(InterpArgs a, KbParams kb) {
+__device__ __forceinline__ void interp_body(const InterpArgs& a, const KbParams& kb, int64_t gid) {
     const int ncg = a.C / CH;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= a.M * ncg) return;
     const int64_t s = gid / ncg;
     const int c0 = (int)(gid % ncg) * CH;
@@ -198,6 +197,36 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, KbParams kb) {
     }
 }
 
+template <int D, int W, int CH>
+__global__ void __launch_bounds__(256) k_interp(InterpArgs a, KbParams kb) {
+    interp_body<D, W, CH>(a, kb, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// find s with start[s] <= b < start[s+1] (start has n+1 entries)
+__device__ __forceinline__ int batch_slot(const int64_t* start, int n, int64_t b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// interpolation of many slices in one launch (2D, width 4, coil groups of 4)
+__global__ void __launch_bounds__(256) k_interp_batch(const InterpArgs* __restrict__ args,
+                                                      const int64_t* __restrict__ start, int n, KbParams kb) {
+    const int s = batch_slot(start, n, blockIdx.x);
+    const InterpArgs a = args[s];
+    interp_body<2, 4, 4>(a, kb, (int64_t)(blockIdx.x - start[s]) * blockDim.x + threadIdx.x);
+}
+
+void launch_interp_batch(const InterpArgs* d_args, const int64_t* d_start, int n, int64_t nblk, const KbParams& kb,
+                         hipStream_t s) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL(k_interp_batch, dim3((unsigned)nblk), dim3(256), 0, s, d_args, d_start, n, kb);
+    KP_LAUNCH_CHECK();
+}
+
 template <int D, int W>
 static void interp_dispatch_ch(const InterpArgs& a, const KbParams& kb, hipStream_t s) {
     const int CH = a.C % 4 == 0 ? 4 : (a.C % 2 == 0 ? 2 : 1);
@@ -244,8 +273,7 @@ size_t spread_lds_bytes(int d, int W, const int* B, int C) {
 }
 
 template <int D, int W, int CG>
-__global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
-    extern __shared__ int smem[];
+__device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams& kb, int64_t item, int* smem) {
     constexpr int E = kSpreadChunk;
     constexpr int NLW = (D - 1) * W;  // leading-axis weights per entry
     const int C = a.C;
@@ -262,7 +290,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
     int* bstart = order + E;
     int* cursor = bstart + NBK + 1;
 
-    const int4 wk = a.work[blockIdx.x];
+    const int4 wk = a.work[item];
     const int tile = wk.x, start = wk.y, count = wk.z, slot = wk.w;
     int tc[3] = {0, 0, 0};
     {
@@ -467,6 +495,68 @@ void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, 
     if (nheavy <= 0) return;
     const int64_t n = (int64_t)a.B[0] * (d == 3 ? a.B[1] : 1) * a.B[d - 1] * a.C;
     hipLaunchKernelGGL(k_reduce_partials, dim3(nheavy, (unsigned)((n + 255) / 256)), dim3(256), 0, s, a, heavy, d);
+    KP_LAUNCH_CHECK();
+}
+
+template <int D, int W, int CG>
+__global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
+    extern __shared__ int smem[];
+    spread_body<D, W, CG>(a, kb, blockIdx.x, smem);
+}
+
+// spreading of many slices in one launch (2D, width 4, coil groups of 4): the
+// work items of slice s are blocks start[s] .. start[s+1]-1
+__global__ void __launch_bounds__(256) k_spread_batch(const SpreadArgs* __restrict__ args,
+                                                      const int64_t* __restrict__ start, int n, KbParams kb) {
+    extern __shared__ int smem[];
+    const int s = batch_slot(start, n, blockIdx.x);
+    const SpreadArgs a = args[s];
+    spread_body<2, 4, 4>(a, kb, blockIdx.x - start[s], smem);
+}
+
+void launch_spread_batch(const SpreadArgs* d_args, const int64_t* d_start, int n, int64_t nblk, int threads,
+                         size_t lds, const KbParams& kb, hipStream_t s) {
+    if (nblk <= 0) return;
+    if (lds > 65536) {
+        (void)hipFuncSetAttribute((const void*)k_spread_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_spread_batch, dim3((unsigned)nblk), dim3(threads), lds, s, d_args, d_start, n, kb);
+    KP_LAUNCH_CHECK();
+}
+
+// partial-tile reduction of many slices: entry h = (slice, heavy index)
+__global__ void k_reduce_batch(const SpreadArgs* __restrict__ args, const int2* __restrict__ hv,
+                               const int4* const* __restrict__ heavy_lists) {
+    const int2 e = hv[blockIdx.x];
+    const SpreadArgs& a = args[e.x];
+    const int4 h = heavy_lists[e.x][e.y];
+    const int B0 = a.B[0], B1 = a.B[1], ZL = a.B[1];
+    (void)B1;
+    const int C = a.C;
+    const int64_t cells = (int64_t)B0 * ZL;
+    const int tc0 = h.x / a.nb[1], tc1 = h.x % a.nb[1];
+    for (int64_t i = threadIdx.x; i < cells * C; i += blockDim.x) {
+        const float2* src = a.partial + (int64_t)h.y * cells * C + i;
+        float2 sm = make_float2(0.f, 0.f);
+        for (int q = 0; q < h.z; ++q) {
+            const float2 v = src[(int64_t)q * cells * C];
+            sm.x += v.x;
+            sm.y += v.y;
+        }
+        const int64_t cell = i / C;
+        const int c = (int)(i % C);
+        const int z = (int)(cell % ZL);
+        const int64_t line = cell / ZL;
+        const int64_t row = (int64_t)(tc0 * B0 + line) * a.G[1] + tc1 * ZL;
+        a.grid[(row + z) * C + c] = sm;
+    }
+}
+
+void launch_reduce_batch(const SpreadArgs* d_args, const int2* d_hv, const int4* const* d_lists, int nh,
+                         hipStream_t s) {
+    if (nh <= 0) return;
+    hipLaunchKernelGGL(k_reduce_batch, dim3(nh), dim3(256), 0, s, d_args, d_hv, d_lists);
     KP_LAUNCH_CHECK();
 }
 

@@ -238,6 +238,26 @@ void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStre
 
 void interp(Plan& P, const float2* grid, const InterpArgs& tmpl, hipStream_t s);
 
+// descriptor builders (what forward_to_grid / grid_to_image / spread_to_grid /
+// interp launch), used to assemble one-launch-per-phase batches
+std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o);
+std::vector<FftPass> adjoint_passes(Plan& P, float2* grid, float2* out, const AdjOpts& o);
+SpreadArgs spread_args(Plan& P, const float2* kint, int C);
+InterpArgs interp_args(Plan& P, const float2* grid, const InterpArgs& tmpl);
+
+// batched launches (fft.hip, grid.hip)
+bool fft_batchable(const FftPass& p);
+int64_t fft_pass_blocks(const FftPass& p);
+void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n, int64_t nblk, int maxL, int nc,
+                      hipStream_t s);
+void launch_interp_batch(const InterpArgs* d_args, const int64_t* d_start, int n, int64_t nblk, const KbParams& kb,
+                         hipStream_t s);
+void launch_spread_batch(const SpreadArgs* d_args, const int64_t* d_start, int n, int64_t nblk, int threads,
+                         size_t lds, const KbParams& kb, hipStream_t s);
+void launch_reduce_batch(const SpreadArgs* d_args, const int2* d_hv, const int4* const* d_lists, int nh,
+                         hipStream_t s);
+void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, hipStream_t s);
+
 // Elementwise helpers (solver.hip)
 void permute_to_internal(const float2* y_caller, float2* kint, const int32_t* perm, int64_t M,
                          int C, hipStream_t s);

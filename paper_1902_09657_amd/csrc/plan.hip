@@ -658,12 +658,13 @@ static void fill_stages(const Plan& P, int ax, FftPass& fp) {
     fp.tw = P.tw[ax].as<float2>();
 }
 
-float2* forward_to_grid(Plan& P, const float2* x, const FwdOpts& o, hipStream_t s) {
+std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o) {
     const int C = o.C < 0 ? (int)P.C : o.C;
     const int d = P.d;
     float2* bufs[2] = {P.bufA.as<float2>(), P.bufB.as<float2>()};
     int which = 0;
     const float2* prev = nullptr;
+    std::vector<FftPass> out;
     for (int p = 0; p < d; ++p) {
         const int ax = d - 1 - p;
         FftPass fp{};
@@ -696,17 +697,24 @@ float2* forward_to_grid(Plan& P, const float2* x, const FwdOpts& o, hipStream_t 
             fp.in = prev;
         }
         pass_blocking(I, &fp.Ob, &fp.Ib);
-        launch_fft_pass(fp, s);
+        out.push_back(fp);
         prev = fp.out;
         which ^= 1;
     }
-    return const_cast<float2*>(prev);
+    return out;
 }
 
-void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStream_t s) {
+float2* forward_to_grid(Plan& P, const float2* x, const FwdOpts& o, hipStream_t s) {
+    const std::vector<FftPass> ps = forward_passes(P, x, o);
+    for (const FftPass& fp : ps) launch_fft_pass(fp, s);
+    return ps.back().out;
+}
+
+std::vector<FftPass> adjoint_passes(Plan& P, float2* grid, float2* out, const AdjOpts& o) {
     const int C = o.C < 0 ? (int)P.C : o.C;
     const int d = P.d;
     const float2* cur = grid;
+    std::vector<FftPass> res;
     for (int ax = 0; ax < d; ++ax) {
         float2* dst = (cur == P.bufA.as<float2>()) ? P.bufB.as<float2>() : P.bufA.as<float2>();
         FftPass fp{};
@@ -751,15 +759,19 @@ void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStre
             fp.out = dst;
             pass_blocking(I, &fp.Ob, &fp.Ib);
         }
-        launch_fft_pass(fp, s);
+        res.push_back(fp);
         cur = dst;
     }
+    return res;
 }
 
-float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
-    float2* grid = P.bufA.as<float2>();
+void grid_to_image(Plan& P, float2* grid, float2* out, const AdjOpts& o, hipStream_t s) {
+    for (const FftPass& fp : adjoint_passes(P, grid, out, o)) launch_fft_pass(fp, s);
+}
+
+SpreadArgs spread_args(Plan& P, const float2* kint, int C) {
     SpreadArgs a{};
-    a.grid = grid;
+    a.grid = P.bufA.as<float2>();
     a.g = P.g_sorted.as<float>();
     a.k = kint;
     a.touch = P.touch.as<int32_t>();
@@ -772,9 +784,25 @@ float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
         a.B[ax] = P.B[ax];
         a.nb[ax] = P.nb[ax];
     }
+    return a;
+}
+
+float2* spread_to_grid(Plan& P, const float2* kint, int C, hipStream_t s) {
+    const SpreadArgs a = spread_args(P, kint, C);
     launch_spread(P.d, P.W, a, P.kb, s);
     launch_reduce_partials(a, P.heavy_list.as<int4>(), (int)P.heavy_tiles, P.d, s);
-    return grid;
+    return a.grid;
+}
+
+InterpArgs interp_args(Plan& P, const float2* grid, const InterpArgs& tmpl) {
+    InterpArgs a = tmpl;
+    a.grid = grid;
+    a.g = P.g_sorted.as<float>();
+    a.perm = P.perm.as<int32_t>();
+    a.M = P.M;
+    if (a.C <= 0) a.C = (int)P.C;
+    for (int ax = 0; ax < 3; ++ax) a.G[ax] = P.G[ax];
+    return a;
 }
 
 void interp(Plan& P, const float2* grid, const InterpArgs& tmpl, hipStream_t s) {

@@ -455,8 +455,10 @@ const float* load_p(Plan& P, const float* p, int p_kind, hipStream_t s) {
     return P.pint.as<float>();
 }
 
-void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, float2* x_out,
-                     float2* u_out, hipStream_t s) {
+// Validate options; load y, p, u0, x0 into the plan's internal buffers
+// (kint2, pint, kint, img[0], img[1]); compute min p, lambda_max and the
+// step schedule on the device.
+void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, hipStream_t s) {
     check_p(P, p, p_kind);
     if (op.iters < 1 || op.iters > 8192) fail(KP_ERR_INVALID_ARG, "iters must lie in [1, 8192]");
     if (op.reg != KP_REG_L2 && op.reg != KP_REG_L1_WAVELET) fail(KP_ERR_INVALID_ARG, "unknown regulariser");
@@ -488,7 +490,6 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
         fill2(u, P.M * C, 0.f, 0.f, s);
     float2* x = P.img[0].as<float2>();
     float2* xbar = P.img[1].as<float2>();
-    float2* z = P.img[2].as<float2>();
     if (op.x0)
         copy2((const float2*)op.x0, x, P.Ntot, s);
     else
@@ -511,7 +512,24 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
     hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), slot(P, SL_PMIN), K, op.sigma0,
                        op.accel, sig, tau, th);
     KP_LAUNCH_CHECK();
+}
 
+void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, float2* x_out,
+                     float2* u_out, hipStream_t s) {
+    pdhg_setup(P, y, p, p_kind, op, s);
+    const int C = (int)P.C;
+    const int K = op.iters;
+    const int levels = op.wavelet_levels;
+    const int p_mc = p_kind == KP_PRECOND_MC ? 1 : 0;
+    const float* pint = p_kind == KP_PRECOND_NONE ? nullptr : P.pint.as<float>();
+    float* sig = P.sched.as<float>();
+    float* tau = sig + 8192;
+    float* th = tau + 8192;
+    float2* yint = P.kint2.as<float2>();
+    float2* u = P.kint.as<float2>();
+    float2* x = P.img[0].as<float2>();
+    float2* xbar = P.img[1].as<float2>();
+    float2* z = P.img[2].as<float2>();
     if (op.objective_host) op.objective_host[0] = objective(P, x, yint, op.reg, op.lambda, levels, s);
     for (int k = 0; k < K; ++k) {
         FwdOpts fo;
