@@ -88,6 +88,165 @@ def cpu_baseline(cfg, k, x, maps):
     }
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def bench_batched(kp, dev, reps=3):
+    """64 uneven 2D 12-coil radial slices, l2 PDHG, 20 iterations each: one
+    pdhg_solve_batch (one launch per phase over all slices, iterations in a
+    HIP graph, autotuned tiles) against pdhg_solve slice after slice."""
+    import torch
+    import synth
+    K, C, lam = 20, 12, 1e-3
+    sl = synth.slice_config4(64, seed=4, ncoils=C)
+    log("batched: inputs and data for", len(sl), "slices")
+    coords, maps, ys, xs_true = [], [], [], []
+    for i, (shape, k) in enumerate(sl):
+        rp, rm, _, rn = synth.streams(4000 + i)
+        x = synth.phantom(shape, rp)
+        m = synth.coil_maps(shape, C, rm)
+        kt = torch.from_numpy(k).to(dev)
+        mt = torch.from_numpy(m.astype(np.complex64)).to(dev)
+        hi = kp.nufft_plan(kt, shape, mt, oversamp=2.0, kb_width=8)
+        w = torch.from_numpy(synth.noise((C, k.shape[0]), 1e-3, rn).astype(np.complex64)).to(dev)
+        ys.append(kp.nufft_forward(hi, torch.from_numpy(x.astype(np.complex64)).to(dev)) + w)
+        hi.close()
+        coords.append(kt)
+        maps.append(mt)
+    torch.cuda.synchronize()
+    log("batched: plain plans, preconditioners, lambda_max")
+    plans, ps, lms = [], [], []
+    for (shape, _), kt, mt in zip(sl, coords, maps):
+        pl = kp.nufft_plan(kt, shape, mt, oversamp=1.25, kb_width=4)
+        p = kp.precond_build(pl, kp.KP_PRECOND_MC)
+        lms.append(float(kp.pdhg_lambda_max(pl, p, 30).item()))
+        plans.append(pl)
+        ps.append(p)
+    log("batched: batch plan (autotuned)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = kp.nufft_plan_batch(coords, [s for s, _ in sl], maps, oversamp=1.25, kb_width=4, tune=True)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    fast = all(kp.nufft_batch_info(b, i)["fast"] for i in range(len(sl)))
+    tiles = sorted({kp.nufft_batch_info(b, i)["bin_size"] for i in range(len(sl))})
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    xb = kp.pdhg_solve_batch(b, ys, ps, lam=lam, iters=K, lambda_max=lms)    # captures the graph
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        xb = kp.pdhg_solve_batch(b, ys, ps, lam=lam, iters=K, lambda_max=lms)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1) / 1e3 / reps
+    for i, pl in enumerate(plans):
+        kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=lam, iters=2, lambda_max=lms[i])
+    torch.cuda.synchronize()
+    e0.record(s)
+    xp = [kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=lam, iters=K, lambda_max=lms[i]) for i, pl in enumerate(plans)]
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_p = e0.elapsed_time(e1) / 1e3
+    diff = max(_rel(a, c) for a, c in zip(xb, xp))
+    MC = sum(int(k.shape[0]) for _, k in sl) * C
+    for pl in plans:
+        pl.close()
+    b.close()
+    return {
+        "workload": "64 uneven 2D radial slices, N in {128,192,256,320}, 32-256 spokes x 2N, 12 coils, "
+                    "alpha 1.25, W 4, l2 lambda 1e-3, mc precond, 20 iters",
+        "slices": len(sl), "iters": K, "samples_coil_total": MC, "one_launch_per_phase": fast,
+        "tiles": [list(t) for t in tiles], "plan_s_incl_autotune": round(t_plan, 3),
+        "batched_ms": round(t_b * 1e3, 3), "plain_ms": round(t_p * 1e3, 3),
+        "speedup_vs_plain": round(t_p / t_b, 3),
+        "batched_msamples_coil_per_s": round(MC * K / t_b / 1e6, 1),
+        "plain_msamples_coil_per_s": round(MC * K / t_p / 1e6, 1),
+        "batched_slice_iters_per_s": round(len(sl) * K / t_b, 1),
+        "max_rel_diff_vs_plain": diff,
+    }
+
+
+def bench_differentiable(kp, dev, reps=3):
+    """8 2D 12-coil spiral slices 256^2, 10-step unrolled l2 PDHG with
+    learnable step sizes and lambda, loss 1/2||x_K - x_true||^2, forward and
+    backward through the autograd Function (checkpoints every 4 steps),
+    against the plain 10-iteration pdhg_solve of the same slices."""
+    import torch
+    import synth
+    from paper_1902_09657_amd.autograd import schedule_params, unrolled_pdhg
+    cfg = synth.config(5)
+    K, C, nb = cfg.iters, cfg.ncoils, cfg.extra["batch"]
+    log("differentiable: inputs for", nb, "slices")
+    plans, ys, ps, xt, lms = [], [], [], [], []
+    for i in range(nb):
+        x, m, k, w = cfg.inputs(seed=5000 + i)
+        kt = torch.from_numpy(k).to(dev)
+        mt = torch.from_numpy(m.astype(np.complex64)).to(dev)
+        xg = torch.from_numpy(x.astype(np.complex64)).to(dev)
+        hi = kp.nufft_plan(kt, cfg.shape, mt, oversamp=2.0, kb_width=8)
+        ys.append(kp.nufft_forward(hi, xg) + torch.from_numpy(w.astype(np.complex64)).to(dev))
+        hi.close()
+        pl = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
+        p = kp.precond_build(pl, kp.KP_PRECOND_MC)
+        lms.append(float(kp.pdhg_lambda_max(pl, p, 30).item()))
+        plans.append(pl)
+        ps.append(p)
+        xt.append(xg)
+    params = [schedule_params(pl, ps[i], K, lam=cfg.lam, lambda_max=lms[i]) for i, pl in enumerate(plans)]
+
+    def step():
+        loss = 0.0
+        xs = []
+        for i, pl in enumerate(plans):
+            th = params[i].detach().clone().requires_grad_(True)
+            xk = unrolled_pdhg(ys[i], th, pl, ps[i], K)
+            r = xk - xt[i]
+            li = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+            li.backward()
+            loss = loss + li.detach()
+            xs.append(xk.detach())
+        return xs, loss
+
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    step()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        xs, loss = step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_fb = e0.elapsed_time(e1) / 1e3 / reps
+    xp = [kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=cfg.lam, iters=K, lambda_max=lms[i])
+          for i, pl in enumerate(plans)]
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        xp = [kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=cfg.lam, iters=K, lambda_max=lms[i])
+              for i, pl in enumerate(plans)]
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_p = e0.elapsed_time(e1) / 1e3 / reps
+    diff = max(_rel(a, c) for a, c in zip(xs, xp))
+    ck = kp._lib.load().pdhg_unrolled_ckpt_bytes(plans[0].handle, K, 4)
+    for pl in plans:
+        pl.close()
+    return {
+        "workload": cfg.name + " x%d slices, %d-step unrolled l2 PDHG, learnable steps and lambda" % (nb, K),
+        "fwd_bwd_ms": round(t_fb * 1e3, 3), "plain_solve_ms": round(t_p * 1e3, 3),
+        "fwd_bwd_over_plain": round(t_fb / t_p, 3), "loss": float(loss.item()),
+        "ckpt_bytes_per_slice": int(ck), "max_rel_diff_forward_vs_plain": diff,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +254,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and differentiable forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the per-GPU share is the "
@@ -230,6 +390,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
     plan.close()
+    del plan
+    if not args.no_forms:
+        result["batched"] = bench_batched(kp, dev)
+        result["differentiable"] = bench_differentiable(kp, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one coil)")
         result["cpu_baseline"] = cpu_baseline(cfg, k, x, maps)

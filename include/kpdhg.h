@@ -168,6 +168,14 @@ int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind,
  * recursion; writes g_params float [3K+1], g_y c64 [C][M] (or NULL) and
  * g_x0 c64 [N] (or NULL).  Both use the plan's NUFFT kernels for A and A^H. */
 int64_t pdhg_unrolled_ckpt_bytes(kp_plan_t plan, int K, int ckpt_every);
+
+/* The step sizes pdhg_solve would use, as unrolled parameters: writes
+ * params = device float [3K+1] (K = opts->iters) with sigma_k, tau_k,
+ * theta_k of the schedule above (lambda_max from opts->lambda_max when > 0,
+ * else the power method with opts->power_iters) and lambda = opts->lambda;
+ * the natural initial value of learnable step sizes. */
+int pdhg_schedule_params(kp_plan_t plan, const float* p, int p_kind, const kp_pdhg_opts* opts,
+                         float* params, void* stream);
 int pdhg_unrolled_forward(kp_plan_t plan, const void* y, const float* p, int p_kind,
                           const float* params, int K, int ckpt_every, const void* x0,
                           void* x_out, void* ckpt, void* stream);
@@ -249,13 +257,16 @@ int nufft_batch_info(kp_batch_t batch, int slice, kp_plan_info* info, int* fast)
 /* l2-regularised PDHG (as pdhg_solve with reg = KP_REG_L2, no x0, u0 or
  * objective) on every slice: y, p and x_out are host arrays of nslices
  * device pointers with the per-slice layouts of pdhg_solve (p may be NULL
- * for KP_PRECOND_NONE).  Each slice gets its own lambda_max (power method
- * unless opts->lambda_max > 0) and step schedule.  The K iterations are
+ * for KP_PRECOND_NONE).  Each slice gets its own step schedule from its
+ * own lambda_max: lambda_max[i] (host float [nslices], each > 0) when the
+ * array is given, else opts->lambda_max when > 0, else the power method on
+ * that slice.  The K iterations are
  * captured once into a HIP graph that later calls with the same iters,
  * lambda and p_kind replay; the first call (or one that changes them)
  * allocates the graph and its descriptor tables. */
 int pdhg_solve_batch(kp_batch_t batch, const void* const* y, const float* const* p, int p_kind,
-                     const kp_pdhg_opts* opts, void* const* x_out, void* stream);
+                     const kp_pdhg_opts* opts, const float* lambda_max, void* const* x_out,
+                     void* stream);
 
 /* Release a batch after synchronising the device.  NULL is ignored. */
 void nufft_batch_destroy(kp_batch_t batch);

@@ -283,7 +283,10 @@ def nufft_batch_info(batch: Batch, slice_index: int) -> dict:
 
 def pdhg_solve_batch(batch: Batch, y, p=None, lam=1e-3, iters=20, lambda_max=0.0, power_iters=30, sigma0=1.0,
                      accel=True):
-    """l2 PDHG on every slice; y: list of [C, M_i]; p: None or list of [M_i] / [C, M_i]."""
+    """l2 PDHG on every slice; y: list of [C, M_i]; p: None or list of [M_i] / [C, M_i].
+
+    lambda_max: 0 (power method per slice), one float for every slice, or a
+    list with one value per slice."""
     n = len(batch)
     if len(y) != n or (p is not None and len(p) != n):
         raise ValueError("y and p must have one entry per slice")
@@ -297,13 +300,20 @@ def pdhg_solve_batch(batch: Batch, y, p=None, lam=1e-3, iters=20, lambda_max=0.0
     o.lam = float(lam)
     o.iters = int(iters)
     o.wavelet_levels = 4
-    o.lambda_max = float(lambda_max)
+    lm = None
+    if isinstance(lambda_max, (list, tuple)):
+        if len(lambda_max) != n:
+            raise ValueError("lambda_max must have one entry per slice")
+        lm = (ctypes.c_float * n)(*[float(v) for v in lambda_max])
+        o.lambda_max = 0.0
+    else:
+        o.lambda_max = float(lambda_max)
     o.power_iters = int(power_iters)
     o.sigma0 = float(sigma0)
     o.accel = 1 if accel else 0
     xs = [torch.empty(s, dtype=torch.complex64, device=batch.device) for s in batch.shapes]
     _lib.check(_lib.load().pdhg_solve_batch(batch.handle, _ptr_array(y), _ptr_array(p) if p is not None else None,
-                                            kind, ctypes.byref(o), _ptr_array(xs), _stream()))
+                                            kind, ctypes.byref(o), lm, _ptr_array(xs), _stream()))
     return xs
 
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "pdhg_solve", "pdhg_unrolled_ckpt_bytes", "pdhg_unrolled_forward", "pdhg_unrolled_backward",
     "nufft_destroy", "nufft_plan_info", "nufft_plan_sort", "nufft_plan_grid_coords",
     "kp_db4_filter", "nufft_plan_validate", "kp_last_error", "nufft_stage",
-    "nufft_autotune", "nufft_plan_batch", "nufft_batch_info", "pdhg_solve_batch", "nufft_batch_destroy",
+    "pdhg_schedule_params", "nufft_autotune", "nufft_plan_batch", "nufft_batch_info", "pdhg_solve_batch", "nufft_batch_destroy",
 ]
 KP_STAGE_FWD_FFT, KP_STAGE_INTERP, KP_STAGE_SPREAD, KP_STAGE_ADJ_FFT = 0, 1, 2, 3
 
@@ -109,10 +109,11 @@ def load(path: str = LIB_PATH):
         "nufft_plan_validate": (i32, [i32, P(i64), i64, i64, vp, vp, f32, i32, P(Tuning)]),
         "kp_last_error": (ctypes.c_char_p, []),
         "nufft_stage": (i32, [vp, i32, i32, vp]),
+        "pdhg_schedule_params": (i32, [vp, vp, i32, P(PdhgOpts), vp, vp]),
         "nufft_autotune": (i32, [i32, P(i64), i64, i64, vp, vp, f32, i32, P(Tuning), vp]),
         "nufft_plan_batch": (i32, [P(vp), i32, P(i64), P(i64), i64, P(vp), P(vp), f32, i32, i32, vp]),
         "nufft_batch_info": (i32, [vp, i32, P(PlanInfo), P(i32)]),
-        "pdhg_solve_batch": (i32, [vp, P(vp), P(vp), i32, P(PdhgOpts), P(vp), vp]),
+        "pdhg_solve_batch": (i32, [vp, P(vp), P(vp), i32, P(PdhgOpts), P(f32), P(vp), vp]),
         "nufft_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():

@@ -13,7 +13,7 @@ import math
 import torch
 
 from . import _lib
-from . import Plan, nufft_adjoint, nufft_forward, _p_kind, _ptr, _stream, _dev
+from . import Plan, PdhgOpts, nufft_adjoint, nufft_forward, _p_kind, _ptr, _stream, _dev
 
 
 class SenseNufft(torch.autograd.Function):
@@ -107,3 +107,23 @@ def unrolled_pdhg(y, params, plan, p=None, K=10, ckpt_every=None, x0=None):
     if ckpt_every is None:
         ckpt_every = max(1, math.ceil(math.sqrt(K)))
     return UnrolledPdhg.apply(y, params, plan, p, int(K), int(ckpt_every), x0)
+
+
+def schedule_params(plan: Plan, p=None, K=10, lam=1e-3, lambda_max=0.0, sigma0=1.0, accel=True, power_iters=30):
+    """float32 [3K+1]: the step sizes pdhg_solve would take (and lambda), as
+    the initial value of learnable unrolled parameters."""
+    import ctypes
+    if p is not None:
+        p = _dev(p, torch.float32, "p")
+    o = PdhgOpts()
+    o.reg = _lib.KP_REG_L2
+    o.lam = float(lam)
+    o.iters = int(K)
+    o.lambda_max = float(lambda_max)
+    o.power_iters = int(power_iters)
+    o.sigma0 = float(sigma0)
+    o.accel = 1 if accel else 0
+    params = torch.empty(3 * int(K) + 1, dtype=torch.float32, device=plan.device)
+    _lib.check(_lib.load().pdhg_schedule_params(plan.handle, _ptr(p), _p_kind(p), ctypes.byref(o), _ptr(params),
+                                                _stream()))
+    return params

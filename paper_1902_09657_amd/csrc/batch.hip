@@ -408,7 +408,7 @@ int nufft_batch_info(kp_batch_t batch, int slice, kp_plan_info* info, int* fast)
 }
 
 int pdhg_solve_batch(kp_batch_t batch, const void* const* y, const float* const* p, int p_kind,
-                     const kp_pdhg_opts* opts, void* const* x_out, void* stream) {
+                     const kp_pdhg_opts* opts, const float* lambda_max, void* const* x_out, void* stream) {
     return guarded([&] {
         if (!batch || !batch->impl || !y || !opts || !x_out) fail(KP_ERR_INVALID_ARG, "NULL argument");
         Batch& B = *batch->impl;
@@ -418,8 +418,14 @@ int pdhg_solve_batch(kp_batch_t batch, const void* const* y, const float* const*
         if (p_kind != KP_PRECOND_NONE && !p) fail(KP_ERR_INVALID_ARG, "p is NULL");
         hipStream_t s = (hipStream_t)stream;
         const int n = (int)B.plans.size();
-        for (int i = 0; i < n; ++i)
-            pdhg_setup(*B.plans[i], (const float2*)y[i], p_kind == KP_PRECOND_NONE ? nullptr : p[i], p_kind, op, s);
+        for (int i = 0; i < n; ++i) {
+            kp_pdhg_opts oi = op;
+            if (lambda_max) {
+                if (!(lambda_max[i] > 0.f)) fail(KP_ERR_INVALID_ARG, "lambda_max[i] must be > 0");
+                oi.lambda_max = lambda_max[i];
+            }
+            pdhg_setup(*B.plans[i], (const float2*)y[i], p_kind == KP_PRECOND_NONE ? nullptr : p[i], p_kind, oi, s);
+        }
         if (!(B.exec && B.g_K == op.iters && B.g_pkind == p_kind && B.g_lambda == op.lambda)) {
             if (B.fast)
                 capture_fast(B, op, p_kind, s);

@@ -587,6 +587,39 @@ int pdhg_lambda_max(kp_plan_t plan, const float* p, int p_kind, int iters, float
     });
 }
 
+int pdhg_schedule_params(kp_plan_t plan, const float* p, int p_kind, const kp_pdhg_opts* opts, float* params,
+                         void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl || !opts || !params) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        Plan& P = *plan->impl;
+        const kp_pdhg_opts& op = *opts;
+        check_p(P, p, p_kind);
+        const int K = op.iters;
+        if (K < 1 || K > 8192) fail(KP_ERR_INVALID_ARG, "iters must lie in [1, 8192]");
+        if (!(op.lambda >= 0.f)) fail(KP_ERR_INVALID_ARG, "lambda must be >= 0");
+        if (!(op.sigma0 > 0.f)) fail(KP_ERR_INVALID_ARG, "sigma0 must be > 0");
+        if (op.lambda_max <= 0.f && op.power_iters < 1) fail(KP_ERR_INVALID_ARG, "power_iters must be >= 1");
+        hipStream_t s = (hipStream_t)stream;
+        const int p_mc = p_kind == KP_PRECOND_MC ? 1 : 0;
+        const float* pint = load_p(P, p, p_kind, s);
+        if (pint)
+            reduce_min(pint, P.M * (p_mc ? P.C : 1), slot(P, SL_PMIN), (float*)(P.red.as<double>() + 4096), s);
+        else
+            hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, slot(P, SL_PMIN), 1.f);
+        if (op.lambda_max > 0.f)
+            hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), op.lambda_max);
+        else
+            power_method(P, pint, p_mc, op.power_iters, slot(P, SL_LMAX), s);
+        KP_LAUNCH_CHECK();
+        if (op.lambda_max_out)
+            KP_HIP(hipMemcpyAsync(op.lambda_max_out, slot(P, SL_LMAX), sizeof(float), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), slot(P, SL_PMIN), K, op.sigma0,
+                           op.accel, params, params + K, params + 2 * K);
+        hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, params + 3 * K, op.lambda);
+        KP_LAUNCH_CHECK();
+    });
+}
+
 int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind, const kp_pdhg_opts* opts, void* x_out,
                void* u_out, void* stream) {
     return guarded([&] {

@@ -91,3 +91,25 @@ def test_unrolled_pdhg_forward_and_gradients(S):
     assert rel(yt.grad.cpu().numpy(), g["y"]) < 1e-3
     assert rel(x0t.grad.cpu().numpy(), g["x0"]) < 1e-3
     plan.close()
+
+
+def test_schedule_params_match_solver():
+    from paper_1902_09657_amd.autograd import UnrolledPdhg, schedule_params
+    kp, plan, op, k, maps, x, y = setup(seed=3)
+    shape = op.shape
+    K = 7
+    p = oprecond.efficient_nufft(maps, k, shape, 1.25, 4)
+    pt = dev(p, torch.float32)
+    lmax = opdhg.power_method(op.forward, op.adjoint, p, shape, 30)
+    sig, tau, th = opdhg.schedule(lmax, float(p.min()), K)
+    want = np.concatenate([sig, tau, th, [2e-3]])
+    got = schedule_params(plan, pt, K, lam=2e-3, lambda_max=lmax).cpu().numpy()
+    assert rel(got, want) < 1e-6
+    got_pm = schedule_params(plan, pt, K, lam=2e-3).cpu().numpy()
+    assert rel(got_pm, want) < 1e-4
+    # the unrolled forward with these parameters is the l2 solve
+    yt = dev(y, torch.complex64)
+    xu = UnrolledPdhg.apply(yt, dev(got, torch.float32), plan, pt, K, 3, None)
+    xs = kp.pdhg_solve(plan, yt, pt, reg="l2", lam=2e-3, iters=K, lambda_max=lmax)
+    assert rel(xu.cpu().numpy(), xs.cpu().numpy()) < 1e-5
+    plan.close()

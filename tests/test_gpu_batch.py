@@ -85,11 +85,14 @@ def test_batch_tuned_equals_plain_same_tiles():
     print("batch tuned", flush=True)
     sl = slices([128, 192, 160], [48, 20, 60], 4, 12)
     b = make_batch(kp, sl, tune=True)
-    xb = kp.pdhg_solve_batch(b, [dev(y, torch.complex64) for *_, y in sl], None, lam=1e-2, iters=8)
+    # per-slice lambda_max given by the caller
+    lm = [3.0 + i for i in range(len(sl))]
+    xb = kp.pdhg_solve_batch(b, [dev(y, torch.complex64) for *_, y in sl], None, lam=1e-2, iters=8, lambda_max=lm)
     for i, (sh, k, maps, y) in enumerate(sl):
         inf = kp.nufft_batch_info(b, i)
         assert inf["fast"]
-        xp = plain_solve(kp, sh, k, maps, y, None, 1.25, 4, bin_size=inf["bin_size"], lam=1e-2, iters=8)
+        xp = plain_solve(kp, sh, k, maps, y, None, 1.25, 4, bin_size=inf["bin_size"], lam=1e-2, iters=8,
+                         lambda_max=lm[i])
         r = rel(xb[i].cpu().numpy(), xp.cpu().numpy())
         print("slice", i, sh, inf["bin_size"], "rel", r, flush=True)
         # split sizes may differ from the plain default: summation order only
