@@ -16,7 +16,7 @@ Its continuous Fourier transform, used for deapodisation:
 
     Chat(nu) = sinh( sqrt(beta^2 - (pi W nu)^2) ) / sqrt(beta^2 - (pi W nu)^2)
 
-Pins: Chat against numerical quadrature of C (tests/test_oracle_kb.py); beta
+Pins: Chat against numerical quadrature of C (tests/test_oracle_operators.py); beta
 and C through the NUFFT-vs-NDFT accuracy pins, which fail for a wrong beta or
 kernel normalisation.
 """

@@ -19,7 +19,7 @@ exactly the definition regrouped; no approximation is involved.
 
 Pins: on-grid Cartesian samples reduce to numpy's FFT; the adjoint identity
 to 1e-12; A^H A = I for full Cartesian sampling with unit sum-of-squares maps
-(tests/test_oracle_ndft.py).
+(tests/test_oracle_operators.py).
 """
 from __future__ import annotations
 

@@ -37,7 +37,7 @@ tile T is the ascending list of sorted sample positions whose W^d footprint
 
 Pins: NUFFT vs the exact NDFT on small grids with errors shrinking as W
 grows; adjoint identity to 1e-12; on-grid Cartesian samples; the sort
-against its defining properties (tests/test_oracle_nufft.py).
+against its defining properties (tests/test_oracle_operators.py).
 """
 from __future__ import annotations
 

@@ -38,7 +38,7 @@ Pins: power method vs eigvalsh of the dense A^H P A; l2 PDHG converges to the
 CG solution of (A^H A + lambda I) x = A^H y; duality gap -> 0; the unitary
 special case (single coil, full Cartesian, p = 1) matches the closed-form
 proximal solutions; preconditioned runs end below the unpreconditioned run
-(tests/test_oracle_pdhg.py).
+(tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 

@@ -34,7 +34,7 @@ Pins: definition vs efficient_exact (1e-10); SC closed form vs definition;
 Cartesian full sampling gives p = 1 (SC, and MC with unit sum-of-squares
 maps); MC at C = 1, s = 1 equals SC; p > 0 and invariance to a global map
 phase; efficient_nufft vs definition within the NUFFT error
-(tests/test_oracle_precond.py).
+(tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 

@@ -22,7 +22,7 @@ dL/ds = Re <g_v, dv/ds> = Re sum conj(g_v) dv/ds.
 
 The reverse recursion below is derived by hand from the five lines above,
 step by step in reverse order; it is pinned against float64 central finite
-differences (tests/test_oracle_unrolled.py).
+differences (tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 

@@ -28,7 +28,7 @@ Complex soft threshold: soft(v, t) = v max(1 - t/|v|, 0), and 0 at v = 0.
 Pins: the defining identity |H(e^{i xi})|^2 = 2 cos^8(xi/2) P(sin^2(xi/2))
 at random xi; orthonormality and double-shift orthogonality; four vanishing
 moments; W^T W = I as a dense matrix; perfect reconstruction
-(tests/test_oracle_wavelet.py).
+(tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 
