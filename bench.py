@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and differentiable forms")
+    ap.add_argument("--profile-stages", type=int, default=0, metavar="R",
+                    help="counter-collection mode: build the plan, run each NUFFT stage R times and a plain copy of "
+                         "512 MiB (read) + 512 MiB (write) for calibration, then exit without a JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the per-GPU share is the "
@@ -277,6 +280,20 @@ def main():
     kt = torch.from_numpy(k).to(dev)
     wt = torch.from_numpy(w.astype(np.complex64)).to(dev)
     torch.cuda.synchronize()
+
+    if args.profile_stages > 0:
+        plan = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
+        L = _lib.load()
+        sp = ctypes_stream(torch.cuda.current_stream())
+        for st in (_lib.KP_STAGE_FWD_FFT, _lib.KP_STAGE_INTERP, _lib.KP_STAGE_SPREAD, _lib.KP_STAGE_ADJ_FFT):
+            _lib.check(L.nufft_stage(plan.handle, st, args.profile_stages, sp))
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        plan.close()
+        log("profile stages done")
+        return
 
     # data: a more accurate NUFFT of the phantom plus noise
     log("data")

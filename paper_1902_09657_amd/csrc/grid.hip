@@ -117,6 +117,32 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned nblk) {
     return x * q + min(x, r) + k;
 }
 
+// Output of one (sample, coil group): the interpolated values, or the dual
+// update that consumes them.
+template <int CH>
+__device__ __forceinline__ void interp_store(const InterpArgs& a, int64_t s, int c0, const float2* acc) {
+    const int C = a.C;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int cc = c0 + c;
+        const int64_t e = s * C + cc;
+        if (a.mode == IO_CALLER) {
+            a.out[(int64_t)cc * a.M + a.perm[s]] = acc[c];
+        } else if (a.mode == IO_INTERNAL) {
+            a.out[e] = acc[c];
+        } else if (a.mode == IO_PMUL) {
+            const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+            a.out[e] = make_float2(pv * acc[c].x, pv * acc[c].y);
+        } else {  // IO_DUAL
+            const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+            const float sp = *a.sigma * pv;
+            const float den = 1.f / (1.f + sp);
+            const float2 u = a.u[e], y = a.y[e];
+            a.u[e] = make_float2((u.x + sp * (acc[c].x - y.x)) * den, (u.y + sp * (acc[c].y - y.y)) * den);
+        }
+    }
+}
+
 // ------------------------------------------------------------ interpolation
 // One thread per (sorted sample, group of CH coils), coil group fastest, so
 // the lanes of one sample read one contiguous C-vector per tap.
@@ -175,26 +201,7 @@ __device__ __forceinline__ void interp_body(const InterpArgs& a, const KbParams&
             }
         }
     }
-    // epilogue
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        const int cc = c0 + c;
-        const int64_t e = s * C + cc;
-        if (a.mode == IO_CALLER) {
-            a.out[(int64_t)cc * a.M + a.perm[s]] = acc[c];
-        } else if (a.mode == IO_INTERNAL) {
-            a.out[e] = acc[c];
-        } else if (a.mode == IO_PMUL) {
-            const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-            a.out[e] = make_float2(pv * acc[c].x, pv * acc[c].y);
-        } else {  // IO_DUAL
-            const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-            const float sp = *a.sigma * pv;
-            const float den = 1.f / (1.f + sp);
-            const float2 u = a.u[e], y = a.y[e];
-            a.u[e] = make_float2((u.x + sp * (acc[c].x - y.x)) * den, (u.y + sp * (acc[c].y - y.y)) * den);
-        }
-    }
+    interp_store<CH>(a, s, c0, acc);
 }
 
 template <int D, int W, int CH>
@@ -248,6 +255,314 @@ void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStr
     KP_INTERP_W(2, 2) KP_INTERP_W(2, 4) KP_INTERP_W(2, 6) KP_INTERP_W(2, 8)
     KP_INTERP_W(3, 2) KP_INTERP_W(3, 4) KP_INTERP_W(3, 6) KP_INTERP_W(3, 8)
 #undef KP_INTERP_W
+    fail(KP_ERR_UNSUPPORTED, "interp: unsupported (d, W)");
+}
+
+// Tile-staged interpolation.  Samples are sorted by the tile that holds
+// their cell, so the taps of every sample of tile T lie in T's halo: the
+// (B_a + W - 1)-cell box starting W/2 - 1 cells before the tile.  One block
+// per (piece of a tile, group of CG coils) copies that halo into LDS with
+// coalesced loads, then its threads interpolate the piece's samples from LDS.
+// Each grid value is read from memory once per tile instead of once per tap.
+template <int D, int W, int CG>
+__global__ void __launch_bounds__(256) k_interp_tile(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
+    extern __shared__ float2 halo[];
+    const int ncg = a.C / CG;
+    const int item = blockIdx.x / ncg, cg = blockIdx.x % ncg;
+    const int4 wk = items[item];
+    const int tile = wk.x, start = wk.y, count = wk.z;
+    int org[3] = {0, 0, 0}, H[3] = {1, 1, 1};
+    {
+        int rem = tile;
+        for (int ax = D - 1; ax >= 0; --ax) {
+            org[ax] = (rem % a.nb[ax]) * a.B[ax];
+            rem /= a.nb[ax];
+        }
+    }
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) H[ax] = a.B[ax] + W - 1;
+    const int hcells = H[0] * H[1] * H[2];
+    const int C = a.C;
+    // ---- stage the halo (coil group cg), wrapping periodically
+    constexpr int V = CG >= 2 ? 2 : 1;  // coils per load
+    for (int i = threadIdx.x; i < hcells * (CG / V); i += blockDim.x) {
+        const int cell = i / (CG / V), part = i % (CG / V);
+        int h[3], rem = cell;
+        for (int ax = D - 1; ax >= 0; --ax) {
+            h[ax] = rem % H[ax];
+            rem /= H[ax];
+        }
+        int64_t gi = 0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            int j = org[ax] - W / 2 + 1 + h[ax];
+            j = j < 0 ? j + a.G[ax] : (j >= a.G[ax] ? j - a.G[ax] : j);
+            gi = gi * a.G[ax] + j;
+        }
+        const float2* src = a.grid + gi * C + cg * CG + part * V;
+        if (V == 2) {
+            const float4 v = *reinterpret_cast<const float4*>(src);
+            halo[cell * CG + part * 2] = make_float2(v.x, v.y);
+            halo[cell * CG + part * 2 + 1] = make_float2(v.z, v.w);
+        } else {
+            halo[cell * CG + part] = *src;
+        }
+    }
+    __syncthreads();
+    // ---- interpolate the piece's samples from LDS
+    for (int64_t s = start + threadIdx.x; s < start + count; s += blockDim.x) {
+        float w[D][W];
+        int l[D];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            const float g = a.g[s * D + ax];
+            const float cf = floorf(g);
+            tap_weights<W>(g - cf, kb, w[ax]);
+            l[ax] = (int)cf - org[ax];  // halo index of the first tap
+        }
+        float2 acc[CG];
+#pragma unroll
+        for (int c = 0; c < CG; ++c) acc[c] = make_float2(0.f, 0.f);
+        if (D == 2) {
+#pragma unroll
+            for (int t0 = 0; t0 < W; ++t0) {
+                const int r0 = (l[0] + t0) * H[1] + l[1];
+#pragma unroll
+                for (int t1 = 0; t1 < W; ++t1) {
+                    const float wt = w[0][t0] * w[1][t1];
+                    const float2* src = halo + (r0 + t1) * CG;
+#pragma unroll
+                    for (int c = 0; c < CG; ++c) {
+                        const float2 v = src[c];
+                        acc[c].x = fmaf(wt, v.x, acc[c].x);
+                        acc[c].y = fmaf(wt, v.y, acc[c].y);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int t0 = 0; t0 < W; ++t0) {
+                float wa = w[0][0];
+#pragma unroll
+                for (int q = 1; q < W; ++q) wa = (t0 == q) ? w[0][q] : wa;
+#pragma unroll
+                for (int t1 = 0; t1 < W; ++t1) {
+                    const int r1 = ((l[0] + t0) * H[1] + l[1] + t1) * H[2] + l[2];
+                    const float w01 = wa * w[1][t1];
+#pragma unroll
+                    for (int t2 = 0; t2 < W; ++t2) {
+                        const float wt = w01 * w[2][t2];
+                        const float2* src = halo + (r1 + t2) * CG;
+#pragma unroll
+                        for (int c = 0; c < CG; ++c) {
+                            const float2 v = src[c];
+                            acc[c].x = fmaf(wt, v.x, acc[c].x);
+                            acc[c].y = fmaf(wt, v.y, acc[c].y);
+                        }
+                    }
+                }
+            }
+        }
+        interp_store<CG>(a, s, cg * CG, acc);
+    }
+}
+
+// 3D, width 4, four coils per block: the lanes of one 16-lane row serve one
+// sample (4 coils x the 4 taps along z), so for each of the 16 (x, y) taps a
+// row reads one contiguous 128-byte run of the halo; rows of one halo line
+// are padded to H2P cells (H2P = 4 mod 8) so that the two rows of a 32-lane
+// LDS pass never meet in a bank when they read neighbouring halo lines.  The
+// weights of up to 256 samples are computed once per batch into an LDS table;
+// the 4 z-tap partial sums of a coil are added by a two-step DPP row shift.
+__device__ __forceinline__ float dpp_row_shr4(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_row_shr8(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ void interp_store1(const InterpArgs& a, int64_t s, int cc, float2 v) {
+    const int64_t e = s * a.C + cc;
+    if (a.mode == IO_CALLER) {
+        a.out[(int64_t)cc * a.M + a.perm[s]] = v;
+    } else if (a.mode == IO_INTERNAL) {
+        a.out[e] = v;
+    } else if (a.mode == IO_PMUL) {
+        const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+        a.out[e] = make_float2(pv * v.x, pv * v.y);
+    } else {  // IO_DUAL
+        const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+        const float sp = *a.sigma * pv;
+        const float den = 1.f / (1.f + sp);
+        const float2 u = a.u[e], y = a.y[e];
+        a.u[e] = make_float2((u.x + sp * (v.x - y.x)) * den, (u.y + sp * (v.y - y.y)) * den);
+    }
+}
+
+constexpr int kTlBatch = 256;  // samples whose weights sit in LDS at a time
+constexpr int kTlStage = 12;   // halo loads per thread held in registers
+
+__host__ __device__ inline int tl_h2p(int H2) { return H2 + ((12 - H2 % 8) % 8); }
+
+__global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
+    extern __shared__ float4 tl_smem[];
+    const int ncg = a.C / 4;
+    const int item = blockIdx.x / ncg, cg = blockIdx.x % ncg;
+    const int4 wk = items[item];
+    const int tile = wk.x, start = wk.y, count = wk.z;
+    int org[3];
+    {
+        int rem = tile;
+        for (int ax = 2; ax >= 0; --ax) {
+            org[ax] = (rem % a.nb[ax]) * a.B[ax];
+            rem /= a.nb[ax];
+        }
+    }
+    const int H0 = a.B[0] + 3, H1 = a.B[1] + 3, H2 = a.B[2] + 3, H2P = tl_h2p(H2);
+    const int hcells = H0 * H1 * H2;
+    float2* halo = reinterpret_cast<float2*>(tl_smem);                    // [H0][H1][H2P][4]
+    float* tab = reinterpret_cast<float*>(halo + (size_t)H0 * H1 * H2P * 4);  // [kTlBatch][16]
+    const int C = a.C;
+    const int tid = threadIdx.x;
+
+    // ---- halo loads into registers (two coils per float4)
+    float4 hv[kTlStage];
+#pragma unroll
+    for (int r = 0; r < kTlStage; ++r) {
+        const int i = tid + r * 256;
+        if (i < hcells * 2) {
+            const int cell = i >> 1, part = i & 1;
+            const int h2 = cell % H2, h01 = cell / H2, h1 = h01 % H1, h0 = h01 / H1;
+            int j0 = org[0] - 1 + h0, j1 = org[1] - 1 + h1, j2 = org[2] - 1 + h2;
+            j0 = j0 < 0 ? j0 + a.G[0] : (j0 >= a.G[0] ? j0 - a.G[0] : j0);
+            j1 = j1 < 0 ? j1 + a.G[1] : (j1 >= a.G[1] ? j1 - a.G[1] : j1);
+            j2 = j2 < 0 ? j2 + a.G[2] : (j2 >= a.G[2] ? j2 - a.G[2] : j2);
+            const int64_t gi = ((int64_t)j0 * a.G[1] + j1) * a.G[2] + j2;
+            hv[r] = *reinterpret_cast<const float4*>(a.grid + gi * C + cg * 4 + part * 2);
+        }
+    }
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 3, t2 = (lane >> 2) & 3, sub = lane >> 4;
+    for (int b0 = 0; b0 < count; b0 += kTlBatch) {
+        const int nbt = min(kTlBatch, count - b0);
+        if (b0 > 0) __syncthreads();  // the previous batch is done with the table
+        // ---- weights and halo base of this batch's samples
+        if (tid < nbt) {
+            const int64_t s = start + b0 + tid;
+            float w[3][4];
+            int l[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const float g = a.g[s * 3 + ax];
+                const float cf = floorf(g);
+                tap_weights<4>(g - cf, kb, w[ax]);
+                l[ax] = (int)cf - org[ax];
+            }
+            float4* row = reinterpret_cast<float4*>(tab + tid * 16);
+            row[0] = make_float4(w[0][0], w[0][1], w[0][2], w[0][3]);
+            row[1] = make_float4(w[1][0], w[1][1], w[1][2], w[1][3]);
+            row[2] = make_float4(w[2][0], w[2][1], w[2][2], w[2][3]);
+            row[3] = make_float4(__int_as_float((l[0] * H1 + l[1]) * H2P + l[2]), 0.f, 0.f, 0.f);
+        }
+        if (b0 == 0) {
+#pragma unroll
+            for (int r = 0; r < kTlStage; ++r) {
+                const int i = tid + r * 256;
+                if (i < hcells * 2) {
+                    const int cell = i >> 1, part = i & 1;
+                    const int h2 = cell % H2, h01 = cell / H2;
+                    float2* dst = halo + ((size_t)h01 * H2P + h2) * 4 + part * 2;
+                    dst[0] = make_float2(hv[r].x, hv[r].y);
+                    dst[1] = make_float2(hv[r].z, hv[r].w);
+                }
+            }
+        }
+        __syncthreads();
+        // ---- one sample per 16-lane row
+        for (int i = wave * 4 + sub; i < nbt; i += 16) {
+            const float* row = tab + i * 16;
+            const float4 w0 = *reinterpret_cast<const float4*>(row);
+            const float4 w1 = *reinterpret_cast<const float4*>(row + 4);
+            const float w2 = row[8 + t2];
+            const int base = __float_as_int(row[12]);
+            const float w0v[4] = {w0.x, w0.y, w0.z, w0.w};
+            const float w1v[4] = {w1.x * w2, w1.y * w2, w1.z * w2, w1.w * w2};
+            const float2* hp = halo + (size_t)(base + t2) * 4 + c;
+            float ax = 0.f, ay = 0.f;
+#pragma unroll
+            for (int t0 = 0; t0 < 4; ++t0) {
+#pragma unroll
+                for (int t1 = 0; t1 < 4; ++t1) {
+                    const float wt = w0v[t0] * w1v[t1];
+                    const float2 v = hp[(size_t)((t0 * H1 + t1) * H2P) * 4];
+                    ax = fmaf(wt, v.x, ax);
+                    ay = fmaf(wt, v.y, ay);
+                }
+            }
+            ax += dpp_row_shr4(ax);
+            ay += dpp_row_shr4(ay);
+            ax += dpp_row_shr8(ax);
+            ay += dpp_row_shr8(ay);
+            if (t2 == 3) interp_store1(a, start + b0 + i, cg * 4 + c, make_float2(ax, ay));
+        }
+    }
+}
+
+size_t interp_tl3_lds_bytes(const int* B) {
+    const int H0 = B[0] + 3, H1 = B[1] + 3, H2P = tl_h2p(B[2] + 3);
+    return (size_t)H0 * H1 * H2P * 4 * sizeof(float2) + (size_t)kTlBatch * 16 * sizeof(float);
+}
+
+bool interp_tl3_ok(int d, int W, const int* B, int C) {
+    return d == 3 && W == 4 && C % 4 == 0 && (B[0] + 3) * (B[1] + 3) * (B[2] + 3) * 2 <= kTlStage * 256 &&
+           interp_tl3_lds_bytes(B) <= 65536;
+}
+
+size_t interp_tile_lds_bytes(int d, int W, const int* B, int C) {
+    const int CG = C % 4 == 0 ? 4 : (C % 2 == 0 ? 2 : 1);
+    size_t cells = 1;
+    for (int ax = 0; ax < d; ++ax) cells *= (size_t)(B[ax] + W - 1);
+    return cells * CG * sizeof(float2);
+}
+
+template <int D, int W>
+static void interp_tile_dispatch(const InterpArgs& a, const int4* items, int64_t nitems, size_t lds, const KbParams& kb,
+                                 hipStream_t s) {
+    const int CG = a.C % 4 == 0 ? 4 : (a.C % 2 == 0 ? 2 : 1);
+    const int64_t nb = nitems * (a.C / CG);
+    if (nb > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "interpolation grid too large");
+    const void* fn = CG == 4 ? (const void*)k_interp_tile<D, W, 4>
+                             : (CG == 2 ? (const void*)k_interp_tile<D, W, 2> : (const void*)k_interp_tile<D, W, 1>);
+    if (lds > 65536) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    if (CG == 4)
+        hipLaunchKernelGGL((k_interp_tile<D, W, 4>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+    else if (CG == 2)
+        hipLaunchKernelGGL((k_interp_tile<D, W, 2>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+    else
+        hipLaunchKernelGGL((k_interp_tile<D, W, 1>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+    KP_LAUNCH_CHECK();
+}
+
+void launch_interp_tiles(int d, int W, const InterpArgs& a, const int4* items, int64_t nitems, const KbParams& kb,
+                         hipStream_t s) {
+    if (a.M <= 0 || nitems <= 0) return;
+    if (interp_tl3_ok(d, W, a.B, a.C)) {
+        const int64_t nb = nitems * (a.C / 4);
+        if (nb > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "interpolation grid too large");
+        hipLaunchKernelGGL(k_interp_tl3, dim3((unsigned)nb), dim3(256), interp_tl3_lds_bytes(a.B), s, a, items, kb);
+        KP_LAUNCH_CHECK();
+        return;
+    }
+    const size_t lds = interp_tile_lds_bytes(d, W, a.B, a.C);
+#define KP_ITILE_W(DD, WW) \
+    if (d == DD && W == WW) return interp_tile_dispatch<DD, WW>(a, items, nitems, lds, kb, s);
+    KP_ITILE_W(2, 2) KP_ITILE_W(2, 4) KP_ITILE_W(2, 6) KP_ITILE_W(2, 8)
+    KP_ITILE_W(3, 2) KP_ITILE_W(3, 4) KP_ITILE_W(3, 6) KP_ITILE_W(3, 8)
+#undef KP_ITILE_W
     fail(KP_ERR_UNSUPPORTED, "interp: unsupported (d, W)");
 }
 

@@ -134,6 +134,9 @@ struct InterpArgs {
     const float* p;           // internal [M][C] (MC) or [M] (SC) or null
     int p_mc;
     const float* sigma;       // device scalar
+    // tile geometry (tile-staged path)
+    int B[3];
+    int nb[3];
 };
 
 struct SpreadArgs {
@@ -157,6 +160,12 @@ int spread_threads(int d, const int* B, int C);
 size_t spread_lds_bytes(int d, int W, const int* B, int C);
 
 void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStream_t s);
+// tile-staged interpolation over pieces (tile, first sorted sample, count, 0)
+constexpr int kInterpPiece = 1024;          // samples per piece at most
+constexpr size_t kInterpTileLds = 65536;    // halo bytes up to which the staged path is used
+size_t interp_tile_lds_bytes(int d, int W, const int* B, int C);
+void launch_interp_tiles(int d, int W, const InterpArgs& a, const int4* items, int64_t nitems, const KbParams& kb,
+                         hipStream_t s);
 void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, hipStream_t s);
 void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, int d, hipStream_t s);
 
@@ -187,6 +196,9 @@ struct Plan {
     DevBuf coords;                // caller's coordinates [M][d]
     DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
     DevBuf partial;               // partial tiles of split tiles
+    DevBuf iwork;                 // interpolation pieces (tile, start, count, 0)
+    int64_t niwork = 0;
+    bool interp_tiles = false;    // tile-staged interpolation in use
     int64_t nslots = 0;
     DevBuf maps;                  // [N][C]
     DevBuf fo_fwd, fr_fwd;        // deapodisation factors for the first/last pass

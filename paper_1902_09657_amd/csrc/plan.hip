@@ -547,6 +547,23 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
         }
     }
     std::stable_sort(light_items.begin(), light_items.end(), [](const int4& x, const int4& y) { return x.z > y.z; });
+
+    // ---- interpolation pieces: the sorted samples of each non-empty tile in
+    // runs of at most kInterpPiece, largest first
+    P->interp_tiles = interp_tile_lds_bytes(d, kb_width, P->B, C) <= kInterpTileLds;
+    if (P->interp_tiles) {
+        std::vector<int> boff(P->nbins + 1);
+        KP_HIP(hipMemcpy(boff.data(), P->bin_off.p, sizeof(int) * (P->nbins + 1), hipMemcpyDeviceToHost));
+        std::vector<int4> pieces;
+        for (int64_t t = 0; t < P->nbins; ++t)
+            for (int q = boff[t]; q < boff[t + 1]; q += kInterpPiece)
+                pieces.push_back(make_int4((int)t, q, std::min(kInterpPiece, boff[t + 1] - q), 0));
+        std::stable_sort(pieces.begin(), pieces.end(), [](const int4& x, const int4& y) { return x.z > y.z; });
+        P->niwork = (int64_t)pieces.size();
+        P->iwork.alloc(sizeof(int4) * std::max<size_t>(pieces.size(), 1));
+        if (!pieces.empty())
+            KP_HIP(hipMemcpy(P->iwork.p, pieces.data(), sizeof(int4) * pieces.size(), hipMemcpyHostToDevice));
+    }
     std::vector<int4> items(heavy_items);
     items.insert(items.end(), light_items.begin(), light_items.end());
     P->nwork = (int64_t)items.size();
@@ -801,19 +818,20 @@ InterpArgs interp_args(Plan& P, const float2* grid, const InterpArgs& tmpl) {
     a.perm = P.perm.as<int32_t>();
     a.M = P.M;
     if (a.C <= 0) a.C = (int)P.C;
-    for (int ax = 0; ax < 3; ++ax) a.G[ax] = P.G[ax];
+    for (int ax = 0; ax < 3; ++ax) {
+        a.G[ax] = P.G[ax];
+        a.B[ax] = P.B[ax];
+        a.nb[ax] = P.nb[ax];
+    }
     return a;
 }
 
 void interp(Plan& P, const float2* grid, const InterpArgs& tmpl, hipStream_t s) {
-    InterpArgs a = tmpl;
-    a.grid = grid;
-    a.g = P.g_sorted.as<float>();
-    a.perm = P.perm.as<int32_t>();
-    a.M = P.M;
-    if (a.C <= 0) a.C = (int)P.C;
-    for (int ax = 0; ax < 3; ++ax) a.G[ax] = P.G[ax];
-    launch_interp(P.d, P.W, a, P.kb, s);
+    const InterpArgs a = interp_args(P, grid, tmpl);
+    if (P.interp_tiles && a.C == (int)P.C)
+        launch_interp_tiles(P.d, P.W, a, P.iwork.as<int4>(), P.niwork, P.kb, s);
+    else
+        launch_interp(P.d, P.W, a, P.kb, s);
 }
 
 // ------------------------------------------------------------ db4 filter

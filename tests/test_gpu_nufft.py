@@ -54,6 +54,9 @@ CASES = [
     ((160, 128), 8, 20000, 1.25, 4),
     ((128, 200), 1, 20000, 2.0, 4),
     ((128, 128, 160), 2, 30000, 1.25, 4),
+    # 3D, coils in groups of four (the tap-lane interpolation)
+    ((24, 32, 40), 4, 6000, 1.25, 4),
+    ((40, 36, 44), 8, 30000, 1.25, 4),
 ]
 
 
@@ -114,6 +117,26 @@ def test_heavy_tiles_split_path():
         yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
         assert rel(yg, op.forward(x)) < 1e-4
         plan.close()
+
+
+@pytest.mark.parametrize("C,bins", [(8, None), (4, (5, 10, 5)), (12, (8, 10, 6))])
+def test_dense_centre_3d(C, bins):
+    """Thousands of samples in one tile: interpolation pieces and weight
+    batches split, spreading tiles split; odd tile shapes."""
+    kp = _kp()
+    shape = (32, 40, 24)
+    k, maps, x, y = case(shape, C, 12000, 15, 1.25, 4)
+    k[200:3400] = 0.0
+    k[5000:5300] = np.float32(-np.pi)
+    print("dense 3d", C, bins, flush=True)
+    op = onufft.Nufft(k, shape, maps, 1.25, 4)
+    kw = {} if bins is None else dict(bin_size=bins)
+    plan = _plan(kp, k, shape, maps, 1.25, 4, **kw)
+    yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
+    assert rel(yg, op.forward(x)) < 1e-4
+    xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
+    assert rel(xg, op.adjoint(y)) < 1e-4
+    plan.close()
 
 
 def test_adjoint_identity_on_gpu():

@@ -96,6 +96,8 @@ SOLVE_CASES = [
     ((32, 48), 4, 3000, 1.25, 4, "l1wav", 5e-3, "mc", 15, 3),
     ((16, 16, 24), 3, 4000, 1.25, 4, "l1wav", 5e-3, "sc", 10, 2),
     ((16, 20, 16), 2, 3000, 1.25, 4, "l2", 1e-2, "none", 10, 2),
+    ((16, 24, 16), 4, 5000, 1.25, 4, "l2", 1e-3, "mc", 10, 2),
+    ((16, 16, 32), 8, 6000, 1.25, 4, "l1wav", 5e-3, "sc", 8, 2),
 ]
 
 
