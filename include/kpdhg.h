@@ -51,10 +51,14 @@ enum {
 enum { KP_PRECOND_NONE = 0, KP_PRECOND_SC = 1, KP_PRECOND_MC = 2 };
 enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1 };
 
-/* Kernel tiling.  Zeros select the built-in choice for the shape. */
+/* Kernel tiling.  Zeros select the built-in choice for the shape.
+ * Samples are sorted by the tile (bin_size) that holds their grid cell; the
+ * interpolation stages each such tile's halo.  Spreading owns the cells of its
+ * own tiles (spread_bin_size), through per-tile touch lists. */
 typedef struct {
-    int bin_size[3];   /* spreading/binning tile edge per axis; must divide G_a */
-    int max_chunk;     /* max touch-list entries per spreading work item        */
+    int bin_size[3];        /* sort / interpolation tile edge per axis; divides G_a */
+    int max_chunk;          /* max touch-list entries per spreading work item        */
+    int spread_bin_size[3]; /* spreading tile edge per axis; divides G_a             */
 } kp_tuning;
 
 /* Shape facts of a plan (filled by nufft_plan_info, host struct). */
@@ -66,12 +70,14 @@ typedef struct {
     int kb_width;
     float oversamp;
     double kb_beta;         /* Kaiser-Bessel shape parameter                  */
-    int bin_size[3];
-    int64_t nbins;          /* number of tiles                                */
-    int64_t ntouch;         /* total tile-touch entries                       */
+    int bin_size[3];        /* sort tiles                                     */
+    int64_t nbins;          /* number of sort tiles                           */
+    int64_t ntouch;         /* total spreading-tile touch entries             */
     int64_t nwork;          /* spreading work items                           */
-    int64_t heavy_tiles;    /* tiles split over several work items            */
+    int64_t heavy_tiles;    /* spreading tiles split over several work items  */
     int64_t workspace_bytes;/* device bytes owned by the plan                 */
+    int spread_bin_size[3]; /* spreading tiles                                */
+    int64_t nspread_tiles;  /* number of spreading tiles                      */
 } kp_plan_info;
 
 /* PDHG options (host struct). */
@@ -191,9 +197,10 @@ void nufft_destroy(kp_plan_t plan);
 int nufft_plan_info(kp_plan_t plan, kp_plan_info* info);
 
 /* Copy the plan's sort to caller buffers (device int32): perm [M] (sorted
- * position -> caller sample index), bin_offsets [nbins+1], touch_offsets
- * [nbins+1] and touch [ntouch] (sorted sample positions, ascending within a
- * tile).  Any pointer may be NULL. */
+ * position -> caller sample index), bin_offsets [nbins+1] (sort tiles),
+ * touch_offsets [nspread_tiles+1] and touch [ntouch] (per spreading tile, the
+ * sorted sample positions whose footprint meets it, ascending).  Any pointer
+ * may be NULL. */
 int nufft_plan_sort(kp_plan_t plan, int32_t* perm, int32_t* bin_offsets,
                     int32_t* touch_offsets, int32_t* touch, void* stream);
 

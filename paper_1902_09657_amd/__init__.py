@@ -59,6 +59,7 @@ class Plan:
             "oversamp": inf.oversamp, "kb_beta": inf.kb_beta, "bin_size": tuple(inf.bin_size[:d]),
             "nbins": inf.nbins, "ntouch": inf.ntouch, "nwork": inf.nwork,
             "heavy_tiles": inf.heavy_tiles, "workspace_bytes": inf.workspace_bytes,
+            "spread_bin_size": tuple(inf.spread_bin_size[:d]), "nspread_tiles": inf.nspread_tiles,
         }
 
     def sort(self):
@@ -67,7 +68,7 @@ class Plan:
         dev = self.device
         perm = torch.empty(self.nsamples, dtype=torch.int32, device=dev)
         boff = torch.empty(inf["nbins"] + 1, dtype=torch.int32, device=dev)
-        toff = torch.empty(inf["nbins"] + 1, dtype=torch.int32, device=dev)
+        toff = torch.empty(inf["nspread_tiles"] + 1, dtype=torch.int32, device=dev)
         touch = torch.empty(max(inf["ntouch"], 1), dtype=torch.int32, device=dev)
         _lib.check(_lib.load().nufft_plan_sort(self.handle, _ptr(perm), _ptr(boff), _ptr(toff), _ptr(touch), _stream()))
         return perm, boff, toff, touch[: inf["ntouch"]]
@@ -89,8 +90,12 @@ class Plan:
             pass
 
 
-def nufft_plan(coords, shape, maps=None, oversamp=1.25, kb_width=4, bin_size=None, max_chunk=0) -> Plan:
-    """Plan for coordinates [M][d] (float32, rad/pixel) and maps [C][*shape] (complex64)."""
+def nufft_plan(coords, shape, maps=None, oversamp=1.25, kb_width=4, bin_size=None, max_chunk=0,
+               spread_bin_size=None) -> Plan:
+    """Plan for coordinates [M][d] (float32, rad/pixel) and maps [C][*shape] (complex64).
+
+    bin_size: sort / interpolation tiles; spread_bin_size: spreading tiles
+    (default: bin_size when that is given, else the built-in choice)."""
     L = _lib.load()
     coords = _dev(coords, torch.float32, "coords")
     shape = tuple(int(n) for n in shape)
@@ -104,10 +109,11 @@ def nufft_plan(coords, shape, maps=None, oversamp=1.25, kb_width=4, bin_size=Non
         if tuple(maps.shape[1:]) != shape:
             raise ValueError("maps must have shape [C, *shape]")
     tun = None
-    if bin_size is not None or max_chunk:
+    if bin_size is not None or max_chunk or spread_bin_size is not None:
         tun = Tuning()
         for a in range(3):
             tun.bin_size[a] = int(bin_size[a]) if bin_size is not None and a < d else 0
+            tun.spread_bin_size[a] = int(spread_bin_size[a]) if spread_bin_size is not None and a < d else 0
         tun.max_chunk = int(max_chunk)
     h = ctypes.c_void_p()
     shp = (ctypes.c_int64 * d)(*shape)
@@ -211,7 +217,8 @@ def nufft_autotune(coords, shape, maps=None, oversamp=1.25, kb_width=4) -> dict:
     shp = (ctypes.c_int64 * d)(*shape)
     _lib.check(_lib.load().nufft_autotune(d, shp, C, coords.shape[0], _ptr(coords), _ptr(maps), float(oversamp),
                                           int(kb_width), ctypes.byref(best), _stream()))
-    return {"bin_size": tuple(best.bin_size[:d]), "max_chunk": best.max_chunk}
+    return {"bin_size": tuple(best.bin_size[:d]), "max_chunk": best.max_chunk,
+            "spread_bin_size": tuple(best.spread_bin_size[:d])}
 
 
 class Batch:
@@ -278,6 +285,7 @@ def nufft_batch_info(batch: Batch, slice_index: int) -> dict:
     return {
         "shape": tuple(inf.shape[:d]), "grid": tuple(inf.grid[:d]), "bin_size": tuple(inf.bin_size[:d]),
         "nwork": inf.nwork, "heavy_tiles": inf.heavy_tiles, "fast": bool(fast.value),
+        "spread_bin_size": tuple(inf.spread_bin_size[:d]),
     }
 
 

@@ -39,7 +39,7 @@ class KpError(RuntimeError):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("bin_size", ctypes.c_int * 3), ("max_chunk", ctypes.c_int)]
+    _fields_ = [("bin_size", ctypes.c_int * 3), ("max_chunk", ctypes.c_int), ("spread_bin_size", ctypes.c_int * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -58,6 +58,8 @@ class PlanInfo(ctypes.Structure):
         ("nwork", ctypes.c_int64),
         ("heavy_tiles", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_int64),
+        ("spread_bin_size", ctypes.c_int * 3),
+        ("nspread_tiles", ctypes.c_int64),
     ]
 
 

@@ -216,8 +216,8 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
         sit[i + 1] = sit[i] + (P.M * (C / 4) + 255) / 256;
         ssp[i + 1] = ssp[i] + P.nwork;
         maxL = std::max(maxL, std::max(P.G[0], P.G[1]));
-        spread_thr = std::max(spread_thr, ((spread_threads(2, P.B, C) + 63) / 64) * 64);
-        spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.B, C));
+        spread_thr = std::max(spread_thr, ((spread_threads(2, P.Bs, C) + 63) / 64) * 64);
+        spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C));
     }
     const int nh = (int)hv.size();
     const DescLayout L = desc_layout(n, K, nh);

@@ -356,30 +356,60 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
     const bool live = o < p.O && i < p.I;
     const float xs = p.xscale ? *p.xscale : 1.f;
 
-    // ---- load (pruned)
+    // ---- load (pruned): every row load of this thread is issued before the
+    // first LDS write, so the block has all its loads in flight at once
+    // (addresses are clamped into range and the values of rows past Lin or of
+    // dead columns are replaced by zeros afterwards, so no load is predicated)
+    constexpr int NR = (L + RS - 1) / RS;
+    float2 v[NR];
+    const int64_t oc = live ? o : 0, ic = live ? i : 0;
+    if (p.pre == PRE_NONE) {
+        const float2* src = p.in + oc * p.in_os + ic;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] = src[(int64_t)min(rb + k * RS, p.Lin - 1) * p.in_rs];
+    } else if (p.pre == PRE_MAPS) {
+        float2 mv[NR];
+        float fr[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int64_t e = oc * p.Lin + min(rb + k * RS, p.Lin - 1);
+            v[k] = p.px[e];
+            mv[k] = p.pmaps[e * p.I + ic];
+            fr[k] = p.fr[min(rb + k * RS, p.Lin - 1)];
+        }
+        const float fo = p.fo[oc] * xs;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] = cscale(cmul(v[k], mv[k]), fo * fr[k]);
+    } else {
+        float fr[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int64_t e = oc * p.Lin + min(rb + k * RS, p.Lin - 1);
+            v[k] = p.px[e * p.I + ic];
+            fr[k] = p.fr[min(rb + k * RS, p.Lin - 1)];
+        }
+        const float fo = p.fo[oc] * xs;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] = cscale(v[k], fo * fr[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (!live) v[k] = make_float2(0.f, 0.f);
     if (p.pad_in) {
         const int g0 = p.Lin / 2, g1 = L - p.Lin + p.Lin / 2;
         for (int q = g0 + rb; q < g1; q += RS) buf[q * LS + col] = make_float2(0.f, 0.f);
     }
-    for (int r = rb; r < p.Lin; r += RS) {
-        float2 v = make_float2(0.f, 0.f);
-        if (live) {
-            if (p.pre == PRE_NONE) {
-                v = p.in[o * p.in_os + r * p.in_rs + i];
-            } else if (p.pre == PRE_MAPS) {
-                const int64_t e = o * p.Lin + r;
-                v = cscale(cmul(p.px[e], p.pmaps[e * p.I + i]), p.fo[o] * p.fr[r] * xs);
-            } else {
-                const int64_t e = o * p.Lin + r;
-                v = cscale(p.px[e * p.I + i], p.fo[o] * p.fr[r] * xs);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = rb + k * RS;
+        if (r < p.Lin) {
+            int pos = r;
+            if (p.pad_in) {
+                pos = r - p.Lin / 2;
+                pos += pos < 0 ? L : 0;
             }
+            buf[pos * LS + col] = v[k];
         }
-        int pos = r;
-        if (p.pad_in) {
-            pos = r - p.Lin / 2;
-            pos += pos < 0 ? L : 0;
-        }
-        buf[pos * LS + col] = v;
     }
     __syncthreads();
 
@@ -450,9 +480,9 @@ __global__ void __launch_bounds__(256) k_fft_fixed(FftPass p) {
 }
 
 // Column blocks of the specialised kernels: NC columns over NT threads with
-// NT a multiple of NC (8 or 16 columns on 256 threads; 12 columns, one
-// 12-coil row, on 192 threads).
-static int fixed_threads(int nc) { return nc == 12 ? 192 : ((nc == 8 || nc == 16) ? 256 : 0); }
+// NT a multiple of NC (8, 16 or 32 columns on 256 threads; 12 columns, one
+// 12-coil row, on 192 threads).  32 columns = 256 contiguous bytes per row.
+static int fixed_threads(int nc) { return nc == 12 ? 192 : ((nc == 8 || nc == 16 || nc == 32) ? 256 : 0); }
 
 // One launch over the passes of many independent transforms (the slices of a
 // batch): block b runs pass s with blk_start[s] <= b < blk_start[s+1].  All
@@ -485,7 +515,7 @@ static bool batch_length(int L) { return L == 160 || L == 200 || L == 240 || L =
 bool fft_batchable(const FftPass& p) {
     const int nc = p.Ob * p.Ib;
     const int nt = fixed_threads(nc);
-    if (nc != 16 && nc != 12) return false;
+    if (nc != 32 && nc != 16 && nc != 12) return false;
     if (p.post == POST_MAPS && (nt % p.Ob) != 0) return false;
     return batch_length(p.L);
 }
@@ -498,13 +528,17 @@ void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n
                       hipStream_t s) {
     if (nblk <= 0) return;
     const size_t lds = sizeof(float2) * (size_t)maxL * (nc + 1);
-    const void* fn = nc == 12 ? (const void*)k_fft_batch<12, 192> : (const void*)k_fft_batch<16, 256>;
+    const void* fn = nc == 12   ? (const void*)k_fft_batch<12, 192>
+                     : nc == 32 ? (const void*)k_fft_batch<32, 256>
+                                : (const void*)k_fft_batch<16, 256>;
     if (lds > 65536) {
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     }
     if (nc == 12)
         hipLaunchKernelGGL((k_fft_batch<12, 192>), dim3((unsigned)nblk), dim3(192), lds, s, d_passes, d_blk_start, n);
+    else if (nc == 32)
+        hipLaunchKernelGGL((k_fft_batch<32, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
     else
         hipLaunchKernelGGL((k_fft_batch<16, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
     KP_LAUNCH_CHECK();
@@ -533,7 +567,10 @@ static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     const int nt = fixed_threads(nc);
     if (nt == 0) return false;
     if (p.post == POST_MAPS && (nt % p.Ob) != 0) return false;
-    fft_kernel_t fn = nc == 16 ? fixed_for<16, 256>(p.L) : (nc == 8 ? fixed_for<8, 256>(p.L) : fixed_for<12, 192>(p.L));
+    fft_kernel_t fn = nc == 32   ? fixed_for<32, 256>(p.L)
+                      : nc == 16 ? fixed_for<16, 256>(p.L)
+                      : nc == 8  ? fixed_for<8, 256>(p.L)
+                                 : fixed_for<12, 192>(p.L);
     if (!fn) return false;
     const size_t lds = sizeof(float2) * (size_t)p.L * (nc + 1);
     if (lds > (size_t)lim) return false;

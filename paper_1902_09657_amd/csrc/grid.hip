@@ -575,19 +575,27 @@ int spread_threads(int d, const int* B, int C) {
 }
 
 // LDS carve-up for a chunk of E entries (all 4-byte words):
-//   code[E] | wl[(d-1) W][E] | wz[kZMax][E] | u[C][E] (float2) | order[E] | bstart[NBK+1] | cursor[NBK]
+//   code[E] | wl[(d-1) W][E] | wz[kZMax][E] | u[C][E] (float2) | bstart[NBK+1]
 // (entry index fastest, so lanes reading different entries hit different banks)
-static int spread_nbk(int d, int W, const int* B) {
+// buckets of a tile: first-tap positions -(W-1) .. B_a - 1 on the leading axes
+int spread_nbk(int d, int W, const int* B) {
     return d == 3 ? (B[0] + W - 1) * (B[1] + W - 1) : (B[0] + W - 1);
 }
+
 size_t spread_lds_bytes(int d, int W, const int* B, int C) {
     const size_t E = kSpreadChunk;
     const size_t nbk = (size_t)spread_nbk(d, W, B);
-    const size_t words = E * (1 + (size_t)(d - 1) * W + kZMax + 2 * (size_t)C + 1) + nbk + 1 + std::max<size_t>(nbk, 256);
+    const size_t words = E * (1 + (size_t)(d - 1) * W + kZMax + 2 * (size_t)C) + nbk + 1;
     return 4 * words;
 }
 
-template <int D, int W, int CG>
+// Owner-gather spreading of one work item (a tile, or a piece of a split
+// tile).  Each thread owns one grid line of the tile along the last axis and
+// a group of CG coils, and keeps up to kZMax cells x CG coils in registers.
+// Entries arrive in chunks of E, already ordered by the bucket of their first
+// tap on the leading axes (plan time), so the entries that reach a line form
+// W contiguous runs of the chunk; a binary search per bucket finds them.
+template <int D, int W, int CG, int ZM = kZMax>
 __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams& kb, int64_t item, int* smem) {
     constexpr int E = kSpreadChunk;
     constexpr int NLW = (D - 1) * W;  // leading-axis weights per entry
@@ -601,9 +609,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
     float* wl = (float*)(code + E);
     float* wz = wl + E * NLW;
     float2* uu = (float2*)(wz + E * kZMax);
-    int* order = (int*)(uu + E * C);
-    int* bstart = order + E;
-    int* cursor = bstart + NBK + 1;
+    int* bstart = (int*)(uu + E * C);
 
     const int4 wk = a.work[item];
     const int tile = wk.x, start = wk.y, count = wk.z, slot = wk.w;
@@ -626,37 +632,34 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
     const int j0 = D == 3 ? line / B1 : line;
     const int j1 = D == 3 ? line % B1 : 0;
 
-    float2 acc[kZMax][CG];
+    float2 acc[ZM][CG];
 #pragma unroll
-    for (int z = 0; z < kZMax; ++z)
+    for (int z = 0; z < ZM; ++z)
 #pragma unroll
         for (int c = 0; c < CG; ++c) acc[z][c] = make_float2(0.f, 0.f);
 
     for (int c0 = 0; c0 < count; c0 += E) {
         const int n = min(E, count - c0);
-        // ---- A: stage the chunk: bucket code, weights, coil values
-        for (int i = tid; i <= NBK; i += blockDim.x) bstart[i] = 0;
-        __syncthreads();
+        if (c0 > 0) __syncthreads();  // the previous chunk is consumed
+        // ---- A: stage the chunk: bucket, weights, coil values
         for (int e = tid; e < n; e += blockDim.x) {
             const int s = a.touch[start + c0 + e];
-            int bk = 0;
+            const int bk = a.code[start + c0 + e];
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
                 const float g = a.g[(int64_t)s * D + ax];
                 const float cf = floorf(g);
                 float w[W];
                 tap_weights<W>(g - cf, kb, w);
-                const int Ga = a.G[ax];
-                int l = (int)cf - W / 2 + 1 - org[ax];
-                if (l < -(W - 1)) l += Ga;
-                else if (l > a.B[ax] - 1) l -= Ga;
                 if (ax < D - 1) {
 #pragma unroll
                     for (int t = 0; t < W; ++t) wl[(ax * W + t) * E + e] = w[t];
-                    bk = (ax == 0) ? (l + W - 1) : bk * NB1 + (l + W - 1);
                 } else {
+                    int l = (int)cf - W / 2 + 1 - org[ax];
+                    if (l < -(W - 1)) l += a.G[ax];
+                    else if (l > a.B[ax] - 1) l -= a.G[ax];
 #pragma unroll
-                    for (int z = 0; z < kZMax; ++z) {
+                    for (int z = 0; z < ZM; ++z) {
                         const int t = z - l;
                         float v = 0.f;
 #pragma unroll
@@ -665,46 +668,27 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
                     }
                 }
             }
-            // low 16 bits: bucket; high bits: axis-1 bucket coordinate (3D)
+            // low 16 bits: bucket; high bits: its axis-1 coordinate (3D)
             code[e] = bk | ((D == 3 ? bk % NB1 : 0) << 16);
             const float2* src = a.k + (int64_t)s * C;
             for (int c = 0; c < C; ++c) uu[c * E + e] = src[c];
-            atomicAdd(&bstart[bk + 1], 1);
         }
         __syncthreads();
-        // ---- B: bucket offsets (exclusive scan) and counting-sort scatter
-        {
-            // inclusive scan of bstart[0..NBK] (bstart[0] = 0): each thread
-            // sums a run of buckets, then a Hillis-Steele scan of the run sums
-            const int nt = blockDim.x;
-            const int per = (NBK + 1 + nt - 1) / nt;
-            const int b0 = tid * per, b1 = min(NBK + 1, b0 + per);
-            int sum = 0;
-            for (int b = b0; b < b1; ++b) sum += bstart[b];
-            cursor[tid] = sum;
-            __syncthreads();
-            for (int off = 1; off < nt; off <<= 1) {
-                const int v = tid >= off ? cursor[tid - off] : 0;
-                __syncthreads();
-                cursor[tid] += v;
-                __syncthreads();
+        // ---- B: first entry of every bucket (the chunk is sorted by bucket)
+        for (int b = tid; b <= NBK; b += blockDim.x) {
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((code[mid] & 0xffff) < b) lo = mid + 1; else hi = mid;
             }
-            int run = tid > 0 ? cursor[tid - 1] : 0;
-            for (int b = b0; b < b1; ++b) {
-                run += bstart[b];
-                bstart[b] = run;
-            }
+            bstart[b] = lo;
         }
-        __syncthreads();
-        for (int b = tid; b < NBK; b += blockDim.x) cursor[b] = bstart[b];
-        __syncthreads();
-        for (int e = tid; e < n; e += blockDim.x) order[atomicAdd(&cursor[code[e] & 0xffff], 1)] = e;
         __syncthreads();
         // ---- C: each owner thread gathers the entries covering its line
         if (owner) {
             // the W buckets of one q0 along axis 1 are consecutive, so their
-            // entries form one contiguous run of the sorted order; the axis-1
-            // tap of an entry follows from its bucket coordinate b1
+            // entries form one contiguous run; the axis-1 tap of an entry
+            // follows from its bucket coordinate b1
             auto gather = [&](int idx, int t0) {
                 float wA = wl[t0 * E + idx];
                 if (D == 3) wA *= wl[(W + j1 + W - 1 - (code[idx] >> 16)) * E + idx];
@@ -713,7 +697,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
 #pragma unroll
                 for (int c = 0; c < CG; ++c) uv[c] = up[c * E];
 #pragma unroll
-                for (int z = 0; z < kZMax; ++z) {
+                for (int z = 0; z < ZM; ++z) {
                     const float wt = wA * wz[z * E + idx];
 #pragma unroll
                     for (int c = 0; c < CG; ++c) {
@@ -728,14 +712,12 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
                 const int t0 = W - 1 - q0;
                 int e = e0;
                 for (; e + 1 < e1; e += 2) {
-                    const int i0 = order[e], i1 = order[e + 1];
-                    gather(i0, t0);
-                    gather(i1, t0);
+                    gather(e, t0);
+                    gather(e + 1, t0);
                 }
-                if (e < e1) gather(order[e], t0);
+                if (e < e1) gather(e, t0);
             }
         }
-        __syncthreads();
     }
 
     // ---- D: write the owned lines back
@@ -750,7 +732,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
         const int64_t cells = (int64_t)B0 * B1 * ZL;
         float2* base = slot < 0 ? a.grid + row * C : a.partial + ((int64_t)slot * cells + (int64_t)line * ZL) * C;
 #pragma unroll
-        for (int z = 0; z < kZMax; ++z) {
+        for (int z = 0; z < ZM; ++z) {
             if (z >= ZL) break;
             float2* dst = base + (int64_t)z * C + cg * CG;
 #pragma unroll
@@ -813,10 +795,10 @@ void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, 
     KP_LAUNCH_CHECK();
 }
 
-template <int D, int W, int CG>
+template <int D, int W, int CG, int ZM>
 __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
     extern __shared__ int smem[];
-    spread_body<D, W, CG>(a, kb, blockIdx.x, smem);
+    spread_body<D, W, CG, ZM>(a, kb, blockIdx.x, smem);
 }
 
 // spreading of many slices in one launch (2D, width 4, coil groups of 4): the
@@ -875,25 +857,33 @@ void launch_reduce_batch(const SpreadArgs* d_args, const int2* d_hv, const int4*
     KP_LAUNCH_CHECK();
 }
 
+template <int D, int W, int ZM>
+static void spread_dispatch_z(const SpreadArgs& a, const KbParams& kb, size_t lds, int block, hipStream_t s) {
+    const int CG = coil_group(a.C);
+    const dim3 grid((unsigned)a.nwork);
+    const void* fn = CG == 4 ? (const void*)k_spread<D, W, 4, ZM>
+                             : (CG == 2 ? (const void*)k_spread<D, W, 2, ZM> : (const void*)k_spread<D, W, 1, ZM>);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (CG == 4)
+        hipLaunchKernelGGL((k_spread<D, W, 4, ZM>), grid, dim3(block), lds, s, a, kb);
+    else if (CG == 2)
+        hipLaunchKernelGGL((k_spread<D, W, 2, ZM>), grid, dim3(block), lds, s, a, kb);
+    else
+        hipLaunchKernelGGL((k_spread<D, W, 1, ZM>), grid, dim3(block), lds, s, a, kb);
+    KP_LAUNCH_CHECK();
+}
+
+// tiles at most 4 cells deep along the last axis keep 4-cell register lines
 template <int D, int W>
 static void spread_dispatch(const SpreadArgs& a, const KbParams& kb, hipStream_t s) {
-    const int CG = coil_group(a.C);
     const size_t lds = spread_lds_bytes(D, W, a.B, a.C);
     const int nthr = spread_threads(D, a.B, a.C);
     const int block = ((nthr + 63) / 64) * 64;
     if (block > 256) fail(KP_ERR_UNSUPPORTED, "spreading tile needs more than 256 threads");
-    const dim3 grid((unsigned)a.nwork);
-    if (CG == 4) {
-        (void)hipFuncSetAttribute((const void*)k_spread<D, W, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_spread<D, W, 4>), grid, dim3(block), lds, s, a, kb);
-    } else if (CG == 2) {
-        (void)hipFuncSetAttribute((const void*)k_spread<D, W, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_spread<D, W, 2>), grid, dim3(block), lds, s, a, kb);
-    } else {
-        (void)hipFuncSetAttribute((const void*)k_spread<D, W, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_spread<D, W, 1>), grid, dim3(block), lds, s, a, kb);
-    }
-    KP_LAUNCH_CHECK();
+    if (a.B[D - 1] <= 4)
+        spread_dispatch_z<D, W, 4>(a, kb, lds, block, s);
+    else
+        spread_dispatch_z<D, W, kZMax>(a, kb, lds, block, s);
 }
 
 void launch_spread(int d, int W, const SpreadArgs& a, const KbParams& kb, hipStream_t s) {

@@ -143,7 +143,8 @@ struct SpreadArgs {
     float2* grid;             // [G][C]
     const float* g;           // sorted coords [M][d]
     const float2* k;          // internal k-space [M][C]
-    const int32_t* touch;     // entries (sorted sample positions)
+    const int32_t* touch;     // entries (sorted sample positions), each tile's in bucket order
+    const uint16_t* code;     // bucket of each entry (first tap, leading axes, local + W - 1)
     const int4* work;         // (tile, start, count, partial slot or -1)
     int64_t nwork;
     float2* partial;          // [slots][tile cells][C] partial tiles of split tiles
@@ -157,6 +158,7 @@ struct SpreadArgs {
 constexpr int kSpreadChunk = 128;   // touch entries staged in LDS at a time
 constexpr int kZMax = 8;            // tile extent along the last axis (max)
 int spread_threads(int d, const int* B, int C);
+int spread_nbk(int d, int W, const int* B);
 size_t spread_lds_bytes(int d, int W, const int* B, int C);
 
 void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStream_t s);
@@ -182,9 +184,12 @@ struct Plan {
     float alpha = 2.f;
     double beta = 0;
     KbParams kb{};
-    int B[3] = {1, 1, 1};
+    int B[3] = {1, 1, 1};         // sort / interpolation tiles
     int nb[3] = {1, 1, 1};
     int64_t nbins = 0;
+    int Bs[3] = {1, 1, 1};        // spreading tiles
+    int nbs[3] = {1, 1, 1};
+    int64_t nstiles = 0;
     int64_t ntouch = 0;
     int64_t nwork = 0;
     int64_t heavy_tiles = 0;
@@ -195,6 +200,7 @@ struct Plan {
 
     DevBuf coords;                // caller's coordinates [M][d]
     DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
+    DevBuf stouch, scode;         // touch entries in spreading order, their buckets
     DevBuf partial;               // partial tiles of split tiles
     DevBuf iwork;                 // interpolation pieces (tile, start, count, 0)
     int64_t niwork = 0;

@@ -280,6 +280,57 @@ __global__ void k_touch_emit(const float* gs, int64_t M, Geom gm, const int* off
             }
 }
 
+// Spreading order: each chunk of kSpreadChunk touch entries (the unit the
+// spreading kernel stages in LDS) is stably sorted by the bucket of its
+// entries' first tap on the leading axes, counted from -(W-1).  One block per
+// chunk = (tile, first entry, count).
+__global__ void __launch_bounds__(kSpreadChunk) k_chunk_order(const float* gs, const int32_t* touch,
+                                                              const int4* chunks, Geom gm, int32_t* stouch,
+                                                              uint16_t* scode) {
+    __shared__ int bk_of[kSpreadChunk];
+    __shared__ int cnt[512];
+    const int4 ch = chunks[blockIdx.x];
+    const int tile = ch.x, start = ch.y, n = ch.z;
+    const int e = threadIdx.x;
+    int tc[3], rem = tile;
+    for (int ax = gm.d - 1; ax >= 0; --ax) {
+        tc[ax] = rem % gm.nb[ax];
+        rem /= gm.nb[ax];
+    }
+    const int NB1 = gm.d == 3 ? gm.B[1] + gm.W - 1 : 1;
+    int bk = 0, s = 0;
+    if (e < n) {
+        s = touch[start + e];
+        for (int ax = 0; ax < gm.d - 1; ++ax) {
+            const int cell = (int)floorf(gs[(int64_t)s * gm.d + ax]);
+            int l = cell - gm.W / 2 + 1 - tc[ax] * gm.B[ax];
+            if (l < -(gm.W - 1)) l += gm.G[ax];
+            else if (l > gm.B[ax] - 1) l -= gm.G[ax];
+            bk = ax == 0 ? l + gm.W - 1 : bk * NB1 + (l + gm.W - 1);
+        }
+        bk_of[e] = bk;
+    }
+    for (int b = e; b < 512; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    if (e < n) atomicAdd(&cnt[bk], 1);
+    __syncthreads();
+    if (e == 0) {
+        int run = 0;
+        for (int b = 0; b < 512; ++b) {
+            const int c = cnt[b];
+            cnt[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    if (e < n) {
+        int pos = cnt[bk];
+        for (int q = 0; q < e; ++q) pos += bk_of[q] == bk;  // stable
+        stouch[start + pos] = s;
+        scode[start + pos] = (uint16_t)bk;
+    }
+}
+
 __global__ void k_maps_transpose(const float2* src, int64_t N, int C, float2* dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N * C) return;
@@ -343,7 +394,7 @@ static double kb_ft_host(double nu, int W, double beta) {
     return z == 0 ? 1.0 : std::sin(z) / z;
 }
 
-static Geom make_geom(const Plan& P) {
+static Geom make_geom(const Plan& P, bool spreading = false) {
     Geom gm{};
     gm.d = P.d;
     gm.W = P.W;
@@ -352,8 +403,8 @@ static Geom make_geom(const Plan& P) {
         gm.Gf[a] = (float)P.G[a];
         gm.half[a] = (float)(P.G[a] / 2);
         gm.c[a] = (float)((double)P.G[a] / (2.0 * M_PI));
-        gm.B[a] = P.B[a];
-        gm.nb[a] = P.nb[a];
+        gm.B[a] = spreading ? P.Bs[a] : P.B[a];
+        gm.nb[a] = spreading ? P.nbs[a] : P.nb[a];
     }
     return gm;
 }
@@ -431,14 +482,16 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
 
     // tiles: the last axis at most kZMax cells (one register line per owner
     // thread); 3D leading axes 8 x 8, 2D leading axis up to 64 lines, within
-    // 256 threads; every B_a divides G_a and leaves G_a >= B_a + W - 1.
+    // 256 threads; every B_a divides G_a and leaves G_a >= B_a + W - 1.  In
+    // 3D the spreading tiles are 4 cells deep along the last axis by default
+    // (a 4-cell register line wastes fewer zero-weight taps), the sort tiles 8.
     const int C = (int)ncoils;
     const int CG = C % 4 == 0 ? 4 : (C % 2 == 0 ? 2 : 1);
     const int ncg = C / CG;
     for (int ax = 0; ax < 3; ++ax) {
         if (ax >= ndim) {
-            P->B[ax] = 1;
-            P->nb[ax] = 1;
+            P->B[ax] = P->Bs[ax] = 1;
+            P->nb[ax] = P->nbs[ax] = 1;
             continue;
         }
         const int cap = std::max(1, P->G[ax] - kb_width + 1);
@@ -454,17 +507,33 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
         if (ax == ndim - 1 && b > kZMax) fail(KP_ERR_INVALID_ARG, "tuning.bin_size on the last axis must be <= 8");
         P->B[ax] = b;
         P->nb[ax] = P->G[ax] / b;
+        int bs;
+        if (tuning && tuning->spread_bin_size[ax] > 0)
+            bs = tuning->spread_bin_size[ax];
+        else if (tuning && tuning->bin_size[ax] > 0)
+            bs = b;
+        else if (ndim == 3 && ax == ndim - 1)
+            bs = pick_bin(P->G[ax], std::min(4, cap));
+        else
+            bs = b;
+        if (bs > cap) fail(KP_ERR_INVALID_ARG, "tuning.spread_bin_size must leave G_a >= bin + W - 1");
+        if (P->G[ax] % bs) fail(KP_ERR_INVALID_ARG, "tuning.spread_bin_size must divide the grid size");
+        if (ax == ndim - 1 && bs > kZMax) fail(KP_ERR_INVALID_ARG, "tuning.spread_bin_size on the last axis must be <= 8");
+        P->Bs[ax] = bs;
+        P->nbs[ax] = P->G[ax] / bs;
     }
     P->nbins = (int64_t)P->nb[0] * P->nb[1] * P->nb[2];
-    if (spread_threads(ndim, P->B, C) > 256) fail(KP_ERR_INVALID_ARG, "tuning.bin_size gives more than 256 threads");
-    P->spread_lds = (int)spread_lds_bytes(ndim, kb_width, P->B, C);
+    P->nstiles = (int64_t)P->nbs[0] * P->nbs[1] * P->nbs[2];
+    if (spread_threads(ndim, P->Bs, C) > 256) fail(KP_ERR_INVALID_ARG, "spreading tiles need more than 256 threads");
+    P->spread_lds = (int)spread_lds_bytes(ndim, kb_width, P->Bs, C);
     if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading chunk does not fit in LDS");
-    if (P->nbins >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");
+    if (P->nbins >= ((int64_t)1 << 31) || P->nstiles >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");
     const int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 1024;
 
     const int64_t M = nsamples;
     const int d = ndim;
     Geom gm = make_geom(*P);
+    const Geom gms = make_geom(*P, true);
 
     // ---- canonical coordinates and bin keys
     P->coords.alloc(sizeof(float) * M * d);
@@ -501,7 +570,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     DevBuf tcnt;
     tcnt.alloc(sizeof(int) * (M + 1));
     KP_HIP(hipMemsetAsync(tcnt.p, 0, sizeof(int) * (M + 1), s));
-    hipLaunchKernelGGL(k_touch_count, dim3(nblk(M)), dim3(256), 0, s, P->g_sorted.as<float>(), M, gm,
+    hipLaunchKernelGGL(k_touch_count, dim3(nblk(M)), dim3(256), 0, s, P->g_sorted.as<float>(), M, gms,
                        tcnt.as<int>());
     KP_LAUNCH_CHECK();
     scan_exclusive(tcnt.as<int>(), tcnt.as<int>(), M + 1, s);
@@ -512,20 +581,20 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     DevBuf tkeys;
     tkeys.alloc(sizeof(uint32_t) * std::max(ntouch, 1));
     P->touch.alloc(sizeof(int32_t) * std::max(ntouch, 1));
-    hipLaunchKernelGGL(k_touch_emit, dim3(nblk(M)), dim3(256), 0, s, P->g_sorted.as<float>(), M, gm,
+    hipLaunchKernelGGL(k_touch_emit, dim3(nblk(M)), dim3(256), 0, s, P->g_sorted.as<float>(), M, gms,
                        tcnt.as<int>(), tkeys.as<uint32_t>(), P->touch.as<int32_t>());
     KP_LAUNCH_CHECK();
-    radix_sort_pairs(tkeys.as<uint32_t>(), P->touch.as<int32_t>(), ntouch, (uint32_t)(P->nbins - 1), s);
-    P->touch_off.alloc(sizeof(int) * (P->nbins + 1));
-    KP_HIP(hipMemsetAsync(P->touch_off.p, 0, sizeof(int) * (P->nbins + 1), s));
+    radix_sort_pairs(tkeys.as<uint32_t>(), P->touch.as<int32_t>(), ntouch, (uint32_t)(P->nstiles - 1), s);
+    P->touch_off.alloc(sizeof(int) * (P->nstiles + 1));
+    KP_HIP(hipMemsetAsync(P->touch_off.p, 0, sizeof(int) * (P->nstiles + 1), s));
     hipLaunchKernelGGL(k_count_keys, dim3(nblk(ntouch)), dim3(256), 0, s, tkeys.as<uint32_t>(), (int64_t)ntouch,
                        P->touch_off.as<int>());
     KP_LAUNCH_CHECK();
-    scan_exclusive(P->touch_off.as<int>(), P->touch_off.as<int>(), P->nbins + 1, s);
+    scan_exclusive(P->touch_off.as<int>(), P->touch_off.as<int>(), P->nstiles + 1, s);
 
     // ---- spreading work items (host): heavy tiles split, largest work first
-    std::vector<int> toff(P->nbins + 1);
-    KP_HIP(hipMemcpyAsync(toff.data(), P->touch_off.p, sizeof(int) * (P->nbins + 1), hipMemcpyDeviceToHost, s));
+    std::vector<int> toff(P->nstiles + 1);
+    KP_HIP(hipMemcpyAsync(toff.data(), P->touch_off.p, sizeof(int) * (P->nstiles + 1), hipMemcpyDeviceToHost, s));
     KP_HIP(hipStreamSynchronize(s));
     // A tile with more entries than max_chunk is split; each piece gets a
     // partial-tile slot.  Work items run longest first (split pieces, then
@@ -535,7 +604,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     std::vector<int4> heavy_items, light_items;
     std::vector<int4> heavy;  // (tile, first slot, slots, 0)
     int nslots = 0;
-    for (int64_t t = 0; t < P->nbins; ++t) {
+    for (int64_t t = 0; t < P->nstiles; ++t) {
         const int o = toff[t], n = toff[t + 1] - toff[t];
         if (n <= max_chunk) {
             light_items.push_back(make_int4((int)t, o, n, -1));
@@ -567,6 +636,27 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     std::vector<int4> items(heavy_items);
     items.insert(items.end(), light_items.begin(), light_items.end());
     P->nwork = (int64_t)items.size();
+
+    // ---- spreading order of the entries inside every chunk of every item
+    {
+        if (spread_nbk(d, kb_width, P->Bs) > 512) fail(KP_ERR_UNSUPPORTED, "too many tile buckets");
+        std::vector<int4> chunks;
+        for (const int4& it : items)
+            for (int q = 0; q < it.z; q += kSpreadChunk)
+                chunks.push_back(make_int4(it.x, it.y + q, std::min(kSpreadChunk, it.z - q), 0));
+        P->stouch.alloc(sizeof(int32_t) * std::max(ntouch, 1));
+        P->scode.alloc(sizeof(uint16_t) * std::max(ntouch, 1));
+        if (!chunks.empty()) {
+            DevBuf dch;
+            dch.alloc(sizeof(int4) * chunks.size());
+            KP_HIP(hipMemcpy(dch.p, chunks.data(), sizeof(int4) * chunks.size(), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_chunk_order, dim3((unsigned)chunks.size()), dim3(kSpreadChunk), 0, s,
+                               P->g_sorted.as<float>(), P->touch.as<int32_t>(), dch.as<int4>(), gms,
+                               P->stouch.as<int32_t>(), P->scode.as<uint16_t>());
+            KP_LAUNCH_CHECK();
+            KP_HIP(hipStreamSynchronize(s));
+        }
+    }
     P->heavy_tiles = (int64_t)heavy.size();
     P->nslots = nslots;
     P->work.alloc(sizeof(int4) * items.size());
@@ -574,7 +664,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     P->heavy_list.alloc(sizeof(int4) * std::max<size_t>(heavy.size(), 1));
     if (!heavy.empty())
         KP_HIP(hipMemcpy(P->heavy_list.p, heavy.data(), sizeof(int4) * heavy.size(), hipMemcpyHostToDevice));
-    P->partial.alloc(sizeof(float2) * std::max<int64_t>(1, (int64_t)nslots * P->B[0] * P->B[1] * P->B[2] * C));
+    P->partial.alloc(sizeof(float2) * std::max<int64_t>(1, (int64_t)nslots * P->Bs[0] * P->Bs[1] * P->Bs[2] * C));
 
     // ---- coil maps, stored [N][C]; unit maps for a single coil without maps
     P->has_maps = maps != nullptr;
@@ -660,7 +750,10 @@ void fft_twiddles(int L, DevBuf& twb) {
 }
 
 void pass_blocking(int64_t I, int* Ob, int* Ib) {
-    if (I >= 16) {
+    if (I >= 32) {
+        *Ib = 32;
+        *Ob = 1;
+    } else if (I >= 16) {
         *Ib = 16;
         *Ob = 1;
     } else {
@@ -791,15 +884,16 @@ SpreadArgs spread_args(Plan& P, const float2* kint, int C) {
     a.grid = P.bufA.as<float2>();
     a.g = P.g_sorted.as<float>();
     a.k = kint;
-    a.touch = P.touch.as<int32_t>();
+    a.touch = P.stouch.as<int32_t>();
+    a.code = P.scode.as<uint16_t>();
     a.work = P.work.as<int4>();
     a.nwork = P.nwork;
     a.partial = P.partial.as<float2>();
     a.C = C;
     for (int ax = 0; ax < 3; ++ax) {
         a.G[ax] = P.G[ax];
-        a.B[ax] = P.B[ax];
-        a.nb[ax] = P.nb[ax];
+        a.B[ax] = P.Bs[ax];
+        a.nb[ax] = P.nbs[ax];
     }
     return a;
 }
@@ -954,7 +1048,9 @@ int nufft_plan_info(kp_plan_t plan, kp_plan_info* info) {
             info->shape[a] = a < P.d ? P.N[a] : 1;
             info->grid[a] = a < P.d ? P.G[a] : 1;
             info->bin_size[a] = P.B[a];
+            info->spread_bin_size[a] = P.Bs[a];
         }
+        info->nspread_tiles = P.nstiles;
         info->ncoils = P.C;
         info->nsamples = P.M;
         info->kb_width = P.W;
@@ -978,7 +1074,7 @@ int nufft_plan_sort(kp_plan_t plan, int32_t* perm, int32_t* bin_offsets, int32_t
         if (bin_offsets)
             KP_HIP(hipMemcpyAsync(bin_offsets, P.bin_off.p, sizeof(int32_t) * (P.nbins + 1), hipMemcpyDeviceToDevice, s));
         if (touch_offsets)
-            KP_HIP(hipMemcpyAsync(touch_offsets, P.touch_off.p, sizeof(int32_t) * (P.nbins + 1), hipMemcpyDeviceToDevice, s));
+            KP_HIP(hipMemcpyAsync(touch_offsets, P.touch_off.p, sizeof(int32_t) * (P.nstiles + 1), hipMemcpyDeviceToDevice, s));
         if (touch && P.ntouch > 0)
             KP_HIP(hipMemcpyAsync(touch, P.touch.p, sizeof(int32_t) * P.ntouch, hipMemcpyDeviceToDevice, s));
     });

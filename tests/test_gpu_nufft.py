@@ -82,7 +82,7 @@ def test_grid_coords_and_sort_bit_exact(shape, C, M, alpha, W):
     perm, boff, toff, touch = [t.cpu().numpy() for t in plan.sort()]
     assert np.array_equal(perm, perm_o)
     assert np.array_equal(boff, off_o)
-    toff_o, touch_o = onufft.tile_touch_lists(g_or[perm_o], G, B, W)
+    toff_o, touch_o = onufft.tile_touch_lists(g_or[perm_o], G, info["spread_bin_size"], W)
     assert np.array_equal(toff, toff_o)
     assert np.array_equal(touch, touch_o)
     plan.close()
@@ -109,8 +109,8 @@ def test_heavy_tiles_split_path():
     k, maps, x, y = case(shape, C, 2500, 13, 1.25, 4)
     k[100:900] = 0.0                     # a dense centre
     op = onufft.Nufft(k, shape, maps, 1.25, 4)
-    for chunk in (7, 64):
-        plan = _plan(kp, k, shape, maps, 1.25, 4, max_chunk=chunk, bin_size=(5, 6))
+    for chunk, bins in ((7, (5, 6)), (64, (5, 6)), (64, (5, 4))):
+        plan = _plan(kp, k, shape, maps, 1.25, 4, max_chunk=chunk, bin_size=bins)
         assert plan.info()["heavy_tiles"] > 0
         xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
         assert rel(xg, op.adjoint(y)) < 1e-4
@@ -119,7 +119,7 @@ def test_heavy_tiles_split_path():
         plan.close()
 
 
-@pytest.mark.parametrize("C,bins", [(8, None), (4, (5, 10, 5)), (12, (8, 10, 6))])
+@pytest.mark.parametrize("C,bins", [(8, None), (4, (5, 10, 5)), (12, (8, 10, 6)), (4, (8, 10, 3))])
 def test_dense_centre_3d(C, bins):
     """Thousands of samples in one tile: interpolation pieces and weight
     batches split, spreading tiles split; odd tile shapes."""
