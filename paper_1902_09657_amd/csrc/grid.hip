@@ -444,6 +444,10 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
 
     const int lane = tid & 63, wave = tid >> 6;
     const int c = lane & 3, t2 = (lane >> 2) & 3, sub = lane >> 4;
+    // halo offsets (in float2) of the 16 (x, y) taps relative to a sample's base
+    int toff[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) toff[t] = (((t >> 2) * H1 + (t & 3)) * H2P) * 4;
     for (int b0 = 0; b0 < count; b0 += kTlBatch) {
         const int nbt = min(kTlBatch, count - b0);
         if (b0 > 0) __syncthreads();  // the previous batch is done with the table
@@ -488,16 +492,18 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             const int base = __float_as_int(row[12]);
             const float w0v[4] = {w0.x, w0.y, w0.z, w0.w};
             const float w1v[4] = {w1.x * w2, w1.y * w2, w1.z * w2, w1.w * w2};
-            const float2* hp = halo + (size_t)(base + t2) * 4 + c;
+            const int hb = (base + t2) * 4 + c;
+            float2 hv[16];  // all 16 reads issued before the first use
+#pragma unroll
+            for (int t = 0; t < 16; ++t) hv[t] = halo[hb + toff[t]];
             float ax = 0.f, ay = 0.f;
 #pragma unroll
             for (int t0 = 0; t0 < 4; ++t0) {
 #pragma unroll
                 for (int t1 = 0; t1 < 4; ++t1) {
                     const float wt = w0v[t0] * w1v[t1];
-                    const float2 v = hp[(size_t)((t0 * H1 + t1) * H2P) * 4];
-                    ax = fmaf(wt, v.x, ax);
-                    ay = fmaf(wt, v.y, ay);
+                    ax = fmaf(wt, hv[t0 * 4 + t1].x, ax);
+                    ay = fmaf(wt, hv[t0 * 4 + t1].y, ay);
                 }
             }
             ax += dpp_row_shr4(ax);

@@ -239,103 +239,118 @@ void upload_wavelet_constants() {
 
 struct DwtArgs {
     float2* x;
-    int64_t S[3];      // element strides of the full image
+    int S[3];          // element strides of the full image
     int n[3];          // extents of the current approximation block
     int d;
     int ax;
     int inverse;
-    int64_t O, I;      // outer / inner counts of the [O][L][I] view
-    int Ob, Ib;
+    int O, I;          // outer / inner counts of the [O][L][I] view
+    int Ob, Ib;        // columns per block: Ob outers x Ib inners (at most 64)
 };
 
-__device__ __forceinline__ int64_t dwt_addr(const DwtArgs& a, int64_t o, int r, int64_t i) {
-    // o enumerates axes < ax, i enumerates axes > ax (C order within each)
-    int64_t off = 0;
-    int64_t rem = o;
-    for (int b = a.ax - 1; b >= 0; --b) {
-        off += (rem % a.n[b]) * a.S[b];
-        rem /= a.n[b];
-    }
-    rem = i;
-    for (int b = a.d - 1; b > a.ax; --b) {
-        off += (rem % a.n[b]) * a.S[b];
-        rem /= a.n[b];
-    }
-    return off + (int64_t)r * a.S[a.ax];
-}
+constexpr int kDwtElems = 4096;              // L x columns staged per block
+constexpr int kDwtPer = kDwtElems / 256;      // elements per thread
 
 // One level along one axis of the approximation block, in place, through LDS.
 // analysis: a[k] = sum_t h[t] x[(2k+t) mod L], d[k] = sum_t g[t] x[(2k+t) mod L]
-// synthesis: its transpose.
+// synthesis: its transpose.  Columns of the [O][L][I] view: o enumerates the
+// axes before `ax`, i the axes after it (C order within each); along the last
+// axis the rows of a column are contiguous, so rows go fastest over threads.
 __global__ void __launch_bounds__(256) k_dwt_axis(DwtArgs a) {
-    extern __shared__ float2 buf[];
+    extern __shared__ float2 buf[];  // [L][ncol]
+    __shared__ int cbase[64];
     const int L = a.n[a.ax];
     const int ncol = a.Ob * a.Ib;
-    const int64_t nIb = (a.I + a.Ib - 1) / a.Ib;
-    const int64_t o0 = (blockIdx.x / nIb) * a.Ob;
-    const int64_t i0 = (blockIdx.x % nIb) * a.Ib;
+    const int nIb = (a.I + a.Ib - 1) / a.Ib;
+    const int o0 = (int)(blockIdx.x / nIb) * a.Ob;
+    const int i0 = (int)(blockIdx.x % nIb) * a.Ib;
+    const int sr = a.S[a.ax];
     const bool last = (a.ax == a.d - 1);
-    // load: for the contiguous axis put rows fastest, otherwise columns
-    for (int idx = threadIdx.x; idx < L * ncol; idx += blockDim.x) {
-        int r, col;
-        if (last) {
-            r = idx % L;
-            col = idx / L;
-        } else {
-            r = idx / ncol;
-            col = idx % ncol;
+    if ((int)threadIdx.x < ncol) {
+        const int col = threadIdx.x;
+        const int o = o0 + col / a.Ib, i = i0 + col % a.Ib;
+        int off = -1;
+        if (o < a.O && i < a.I) {
+            off = 0;
+            int rem = o;
+            for (int b = a.ax - 1; b >= 0; --b) {
+                off += (rem % a.n[b]) * a.S[b];
+                rem /= a.n[b];
+            }
+            rem = i;
+            for (int b = a.d - 1; b > a.ax; --b) {
+                off += (rem % a.n[b]) * a.S[b];
+                rem /= a.n[b];
+            }
         }
-        const int64_t o = o0 + col / a.Ib, i = i0 + col % a.Ib;
-        float2 v = make_float2(0.f, 0.f);
-        if (o < a.O && i < a.I) v = a.x[dwt_addr(a, o, r, i)];
-        buf[r * ncol + col] = v;
+        cbase[col] = off;
+    }
+    __syncthreads();
+    const int total = L * ncol;
+    // ---- load: every load of this thread issued before the LDS writes
+    float2 v[kDwtPer];
+#pragma unroll
+    for (int k = 0; k < kDwtPer; ++k) {
+        const int idx = threadIdx.x + k * 256;
+        const int r = last ? idx % L : idx / ncol;
+        const int col = last ? idx / L : idx % ncol;
+        const int b = idx < total ? cbase[col] : -1;
+        v[k] = b >= 0 ? a.x[b + r * sr] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < kDwtPer; ++k) {
+        const int idx = threadIdx.x + k * 256;
+        if (idx < total) {
+            const int r = last ? idx % L : idx / ncol;
+            const int col = last ? idx / L : idx % ncol;
+            buf[r * ncol + col] = v[k];
+        }
     }
     __syncthreads();
     const int h2 = L / 2;
-    float2 outv[2];
-    // compute into registers, then barrier, then write back in place (global)
-    for (int idx = threadIdx.x; idx < L * ncol; idx += blockDim.x) {
-        int r, col;
-        if (last) {
-            r = idx % L;
-            col = idx / L;
-        } else {
-            r = idx / ncol;
-            col = idx % ncol;
-        }
-        const int64_t o = o0 + col / a.Ib, i = i0 + col % a.Ib;
+    // ---- filter from LDS, write back in place
+#pragma unroll
+    for (int k = 0; k < kDwtPer; ++k) {
+        const int idx = threadIdx.x + k * 256;
+        if (idx >= total) break;
+        const int r = last ? idx % L : idx / ncol;
+        const int col = last ? idx / L : idx % ncol;
+        const int b = cbase[col];
         float2 acc = make_float2(0.f, 0.f);
         if (!a.inverse) {
-            const int k = r < h2 ? r : r - h2;
+            const int kk = r < h2 ? r : r - h2;
             const float* f = r < h2 ? c_h : c_g;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const int src = (2 * k + t) % L;
-                const float2 v = buf[src * ncol + col];
-                acc.x += f[t] * v.x;
-                acc.y += f[t] * v.y;
+                int src = 2 * kk + t;  // < L + 6
+                src = L >= 8 ? (src >= L ? src - L : src) : src % L;
+                const float2 u = buf[src * ncol + col];
+                acc.x += f[t] * u.x;
+                acc.y += f[t] * u.y;
             }
         } else {
             // x[n] = sum_k h[n-2k] a[k] + g[n-2k] d[k], n-2k taken mod L in [0, 8)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = (r & 1) + 2 * q;
-                int k = (r - t) / 2;  // r - t is even
-                k = ((k % h2) + h2) % h2;
-                const float2 va = buf[k * ncol + col];
-                const float2 vd = buf[(h2 + k) * ncol + col];
+                int kk = (r - t) / 2;  // r - t is even; kk >= -4
+                kk = h2 >= 4 ? (kk < 0 ? kk + h2 : kk) : ((kk % h2) + h2) % h2;
+                const float2 va = buf[kk * ncol + col];
+                const float2 vd = buf[(h2 + kk) * ncol + col];
                 acc.x += c_h[t] * va.x + c_g[t] * vd.x;
                 acc.y += c_h[t] * va.y + c_g[t] * vd.y;
             }
         }
-        if (o < a.O && i < a.I) a.x[dwt_addr(a, o, r, i)] = acc;
+        if (b >= 0) a.x[b + r * sr] = acc;
     }
-    (void)outv;
 }
 
 void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s) {
-    int64_t S[3] = {1, 1, 1};
-    for (int b = d - 2; b >= 0; --b) S[b] = S[b + 1] * N[b + 1];
+    int64_t tot = 1;
+    for (int b = 0; b < d; ++b) tot *= N[b];
+    if (tot >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "wavelet: image too large");
+    int S[3] = {1, 1, 1};
+    for (int b = d - 2; b >= 0; --b) S[b] = S[b + 1] * (int)N[b + 1];
     auto run_level = [&](int lev) {
         int n[3] = {1, 1, 1};
         for (int b = 0; b < d; ++b) n[b] = (int)(N[b] >> lev);
@@ -354,15 +369,17 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
             for (int b = 0; b < ax; ++b) a.O *= n[b];
             for (int b = ax + 1; b < d; ++b) a.I *= n[b];
             const int L = n[ax];
+            const int cap = std::max(1, std::min(64, kDwtElems / L));
+            if (L > kDwtElems) fail(KP_ERR_UNSUPPORTED, "wavelet: axis too long");
             if (ax == d - 1) {
                 a.Ib = 1;
-                a.Ob = std::max(1, std::min<int>(64, 4096 / L));
+                a.Ob = cap;
             } else {
-                a.Ib = (int)std::min<int64_t>(a.I, 16);
+                a.Ib = std::min(a.I, std::min(16, cap));
                 a.Ob = 1;
             }
             const int ncol = a.Ob * a.Ib;
-            const int64_t nb = ((a.O + a.Ob - 1) / a.Ob) * ((a.I + a.Ib - 1) / a.Ib);
+            const int64_t nb = ((int64_t)(a.O + a.Ob - 1) / a.Ob) * ((a.I + a.Ib - 1) / a.Ib);
             hipLaunchKernelGGL(k_dwt_axis, dim3((unsigned)nb), dim3(256), sizeof(float2) * L * ncol, s, a);
             KP_LAUNCH_CHECK();
         };
