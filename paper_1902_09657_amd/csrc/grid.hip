@@ -381,24 +381,6 @@ __device__ __forceinline__ float dpp_row_shr8(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
 }
 
-__device__ __forceinline__ void interp_store1(const InterpArgs& a, int64_t s, int cc, float2 v) {
-    const int64_t e = s * a.C + cc;
-    if (a.mode == IO_CALLER) {
-        a.out[(int64_t)cc * a.M + a.perm[s]] = v;
-    } else if (a.mode == IO_INTERNAL) {
-        a.out[e] = v;
-    } else if (a.mode == IO_PMUL) {
-        const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-        a.out[e] = make_float2(pv * v.x, pv * v.y);
-    } else {  // IO_DUAL
-        const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-        const float sp = *a.sigma * pv;
-        const float den = 1.f / (1.f + sp);
-        const float2 u = a.u[e], y = a.y[e];
-        a.u[e] = make_float2((u.x + sp * (v.x - y.x)) * den, (u.y + sp * (v.y - y.y)) * den);
-    }
-}
-
 constexpr int kTlBatch = 256;  // samples whose weights sit in LDS at a time
 constexpr int kTlStage = 12;   // halo loads per thread held in registers
 
@@ -422,6 +404,7 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
     const int hcells = H0 * H1 * H2;
     float2* halo = reinterpret_cast<float2*>(tl_smem);                    // [H0][H1][H2P][4]
     float* tab = reinterpret_cast<float*>(halo + (size_t)H0 * H1 * H2P * 4);  // [kTlBatch][16]
+    float2* obuf = reinterpret_cast<float2*>(tab + kTlBatch * 16);               // [kTlBatch][4]
     const int C = a.C;
     const int tid = threadIdx.x;
 
@@ -510,19 +493,41 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             ay += dpp_row_shr4(ay);
             ax += dpp_row_shr8(ax);
             ay += dpp_row_shr8(ay);
-            if (t2 == 3) interp_store1(a, start + b0 + i, cg * 4 + c, make_float2(ax, ay));
+            if (t2 == 3) obuf[i * 4 + c] = make_float2(ax, ay);
+        }
+        __syncthreads();
+        // ---- output stage of the batch: all threads, consecutive (sample, coil)
+        for (int q = tid; q < nbt * 4; q += 256) {
+            const int64_t s = start + b0 + (q >> 2);
+            const int cc = cg * 4 + (q & 3);
+            const int64_t e = s * C + cc;
+            const float2 v = obuf[q];
+            if (a.mode == IO_CALLER) {
+                a.out[(int64_t)cc * a.M + a.perm[s]] = v;
+            } else if (a.mode == IO_INTERNAL) {
+                a.out[e] = v;
+            } else if (a.mode == IO_PMUL) {
+                const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+                a.out[e] = make_float2(pv * v.x, pv * v.y);
+            } else {  // IO_DUAL
+                const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
+                const float sp = *a.sigma * pv;
+                const float den = 1.f / (1.f + sp);
+                const float2 u = a.u[e], y = a.y[e];
+                a.u[e] = make_float2((u.x + sp * (v.x - y.x)) * den, (u.y + sp * (v.y - y.y)) * den);
+            }
         }
     }
 }
 
 size_t interp_tl3_lds_bytes(const int* B) {
     const int H0 = B[0] + 3, H1 = B[1] + 3, H2P = tl_h2p(B[2] + 3);
-    return (size_t)H0 * H1 * H2P * 4 * sizeof(float2) + (size_t)kTlBatch * 16 * sizeof(float);
+    return (size_t)H0 * H1 * H2P * 4 * sizeof(float2) + (size_t)kTlBatch * (16 * sizeof(float) + 4 * sizeof(float2));
 }
 
 bool interp_tl3_ok(int d, int W, const int* B, int C) {
     return d == 3 && W == 4 && C % 4 == 0 && (B[0] + 3) * (B[1] + 3) * (B[2] + 3) * 2 <= kTlStage * 256 &&
-           interp_tl3_lds_bytes(B) <= 65536;
+           interp_tl3_lds_bytes(B) <= 80 * 1024;
 }
 
 size_t interp_tile_lds_bytes(int d, int W, const int* B, int C) {
@@ -559,7 +564,12 @@ void launch_interp_tiles(int d, int W, const InterpArgs& a, const int4* items, i
     if (interp_tl3_ok(d, W, a.B, a.C)) {
         const int64_t nb = nitems * (a.C / 4);
         if (nb > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "interpolation grid too large");
-        hipLaunchKernelGGL(k_interp_tl3, dim3((unsigned)nb), dim3(256), interp_tl3_lds_bytes(a.B), s, a, items, kb);
+        const size_t lds = interp_tl3_lds_bytes(a.B);
+        if (lds > 65536) {
+            (void)hipFuncSetAttribute((const void*)k_interp_tl3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipGetLastError();
+        }
+        hipLaunchKernelGGL(k_interp_tl3, dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
         KP_LAUNCH_CHECK();
         return;
     }
