@@ -248,74 +248,71 @@ struct DwtArgs {
     int Ob, Ib;        // columns per block: Ob outers x Ib inners (at most 64)
 };
 
-constexpr int kDwtElems = 4096;              // L x columns staged per block
-constexpr int kDwtPer = kDwtElems / 256;      // elements per thread
+constexpr int kDwtK = 16;  // rows per thread at most
+
+// Offset of column/line `c` of the [O][L][I] view: o = c / I enumerates the
+// axes before `ax`, i = c % I the axes after it (C order within each).
+__device__ __forceinline__ int dwt_base(const DwtArgs& a, int o, int i) {
+    int off = 0, rem = o;
+    for (int b = a.ax - 1; b >= 0; --b) {
+        off += (rem % a.n[b]) * a.S[b];
+        rem /= a.n[b];
+    }
+    rem = i;
+    for (int b = a.d - 1; b > a.ax; --b) {
+        off += (rem % a.n[b]) * a.S[b];
+        rem /= a.n[b];
+    }
+    return off;
+}
 
 // One level along one axis of the approximation block, in place, through LDS.
 // analysis: a[k] = sum_t h[t] x[(2k+t) mod L], d[k] = sum_t g[t] x[(2k+t) mod L]
-// synthesis: its transpose.  Columns of the [O][L][I] view: o enumerates the
-// axes before `ax`, i the axes after it (C order within each); along the last
-// axis the rows of a column are contiguous, so rows go fastest over threads.
-__global__ void __launch_bounds__(256) k_dwt_axis(DwtArgs a) {
-    extern __shared__ float2 buf[];  // [L][ncol]
-    __shared__ int cbase[64];
+// synthesis: its transpose.  A block holds NL lines of length L; every thread
+// owns one line and the rows p, p + P, p + 2P, ... of it (P = 256 / NL).
+// Strided axes: lines are NL consecutive inner columns, lanes run across them
+// (coalesced over the columns).  Contiguous (last) axis: lanes run along a
+// line (coalesced over the rows).
+template <bool LAST, int NL>
+__global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
+    extern __shared__ float2 buf[];
+    constexpr int P = 256 / NL;
     const int L = a.n[a.ax];
-    const int ncol = a.Ob * a.Ib;
-    const int nIb = (a.I + a.Ib - 1) / a.Ib;
-    const int o0 = (int)(blockIdx.x / nIb) * a.Ob;
-    const int i0 = (int)(blockIdx.x % nIb) * a.Ib;
+    const int tid = threadIdx.x;
+    const int l = LAST ? tid / P : tid % NL;
+    const int p = LAST ? tid % P : tid / NL;
+    int base = -1;
+    if (LAST) {
+        const int o = blockIdx.x * NL + l;
+        if (o < a.O) base = dwt_base(a, o, 0);
+    } else {
+        const int nIb = (a.I + NL - 1) / NL;
+        const int o = blockIdx.x / nIb, i = (blockIdx.x % nIb) * NL + l;
+        if (i < a.I) base = dwt_base(a, o, i);
+    }
     const int sr = a.S[a.ax];
-    const bool last = (a.ax == a.d - 1);
-    if ((int)threadIdx.x < ncol) {
-        const int col = threadIdx.x;
-        const int o = o0 + col / a.Ib, i = i0 + col % a.Ib;
-        int off = -1;
-        if (o < a.O && i < a.I) {
-            off = 0;
-            int rem = o;
-            for (int b = a.ax - 1; b >= 0; --b) {
-                off += (rem % a.n[b]) * a.S[b];
-                rem /= a.n[b];
-            }
-            rem = i;
-            for (int b = a.d - 1; b > a.ax; --b) {
-                off += (rem % a.n[b]) * a.S[b];
-                rem /= a.n[b];
-            }
-        }
-        cbase[col] = off;
-    }
-    __syncthreads();
-    const int total = L * ncol;
-    // ---- load: every load of this thread issued before the LDS writes
-    float2 v[kDwtPer];
+    // LDS: line-major rows (padded) on the last axis, row-major otherwise
+    const int LP = L + 1;
+    auto lds = [&](int r) { return LAST ? l * LP + r : r * (NL + 1) + l; };
+    float2 v[kDwtK];
+    const int bb = base < 0 ? 0 : base;
 #pragma unroll
-    for (int k = 0; k < kDwtPer; ++k) {
-        const int idx = threadIdx.x + k * 256;
-        const int r = last ? idx % L : idx / ncol;
-        const int col = last ? idx / L : idx % ncol;
-        const int b = idx < total ? cbase[col] : -1;
-        v[k] = b >= 0 ? a.x[b + r * sr] : make_float2(0.f, 0.f);
+    for (int k = 0; k < kDwtK; ++k) {
+        const int r = p + k * P;
+        v[k] = a.x[bb + min(r, L - 1) * sr];
     }
 #pragma unroll
-    for (int k = 0; k < kDwtPer; ++k) {
-        const int idx = threadIdx.x + k * 256;
-        if (idx < total) {
-            const int r = last ? idx % L : idx / ncol;
-            const int col = last ? idx / L : idx % ncol;
-            buf[r * ncol + col] = v[k];
-        }
+    for (int k = 0; k < kDwtK; ++k) {
+        const int r = p + k * P;
+        if (r < L) buf[lds(r)] = v[k];
     }
     __syncthreads();
+    if (base < 0) return;
     const int h2 = L / 2;
-    // ---- filter from LDS, write back in place
 #pragma unroll
-    for (int k = 0; k < kDwtPer; ++k) {
-        const int idx = threadIdx.x + k * 256;
-        if (idx >= total) break;
-        const int r = last ? idx % L : idx / ncol;
-        const int col = last ? idx / L : idx % ncol;
-        const int b = cbase[col];
+    for (int k = 0; k < kDwtK; ++k) {
+        const int r = p + k * P;
+        if (r >= L) break;
         float2 acc = make_float2(0.f, 0.f);
         if (!a.inverse) {
             const int kk = r < h2 ? r : r - h2;
@@ -324,7 +321,7 @@ __global__ void __launch_bounds__(256) k_dwt_axis(DwtArgs a) {
             for (int t = 0; t < 8; ++t) {
                 int src = 2 * kk + t;  // < L + 6
                 src = L >= 8 ? (src >= L ? src - L : src) : src % L;
-                const float2 u = buf[src * ncol + col];
+                const float2 u = buf[lds(src)];
                 acc.x += f[t] * u.x;
                 acc.y += f[t] * u.y;
             }
@@ -335,13 +332,13 @@ __global__ void __launch_bounds__(256) k_dwt_axis(DwtArgs a) {
                 const int t = (r & 1) + 2 * q;
                 int kk = (r - t) / 2;  // r - t is even; kk >= -4
                 kk = h2 >= 4 ? (kk < 0 ? kk + h2 : kk) : ((kk % h2) + h2) % h2;
-                const float2 va = buf[kk * ncol + col];
-                const float2 vd = buf[(h2 + kk) * ncol + col];
+                const float2 va = buf[lds(kk)];
+                const float2 vd = buf[lds(h2 + kk)];
                 acc.x += c_h[t] * va.x + c_g[t] * vd.x;
                 acc.y += c_h[t] * va.y + c_g[t] * vd.y;
             }
         }
-        if (b >= 0) a.x[b + r * sr] = acc;
+        a.x[base + r * sr] = acc;
     }
 }
 
@@ -369,18 +366,29 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
             for (int b = 0; b < ax; ++b) a.O *= n[b];
             for (int b = ax + 1; b < d; ++b) a.I *= n[b];
             const int L = n[ax];
-            const int cap = std::max(1, std::min(64, kDwtElems / L));
-            if (L > kDwtElems) fail(KP_ERR_UNSUPPORTED, "wavelet: axis too long");
-            if (ax == d - 1) {
-                a.Ib = 1;
-                a.Ob = cap;
-            } else {
-                a.Ib = std::min(a.I, std::min(16, cap));
-                a.Ob = 1;
+            // lines per block so that every thread holds at most kDwtK rows
+            int NL;
+            if (ax == d - 1)
+                NL = L <= kDwtK * 32 ? 8 : (L <= kDwtK * 64 ? 4 : 1);
+            else
+                NL = L <= kDwtK * 16 ? 16 : (L <= kDwtK * 64 ? 4 : 1);
+            if (L > kDwtK * 256) fail(KP_ERR_UNSUPPORTED, "wavelet: axis too long");
+            const size_t lds = sizeof(float2) * (ax == d - 1 ? (size_t)NL * (L + 1) : (size_t)L * (NL + 1));
+            int64_t nb;
+            if (ax == d - 1)
+                nb = (a.O + NL - 1) / NL;
+            else
+                nb = (int64_t)a.O * ((a.I + NL - 1) / NL);
+            void (*fn)(DwtArgs);
+            if (ax == d - 1)
+                fn = NL == 8 ? k_dwt_pass<true, 8> : (NL == 4 ? k_dwt_pass<true, 4> : k_dwt_pass<true, 1>);
+            else
+                fn = NL == 16 ? k_dwt_pass<false, 16> : (NL == 4 ? k_dwt_pass<false, 4> : k_dwt_pass<false, 1>);
+            if (lds > 65536) {
+                (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                (void)hipGetLastError();
             }
-            const int ncol = a.Ob * a.Ib;
-            const int64_t nb = ((int64_t)(a.O + a.Ob - 1) / a.Ob) * ((a.I + a.Ib - 1) / a.Ib);
-            hipLaunchKernelGGL(k_dwt_axis, dim3((unsigned)nb), dim3(256), sizeof(float2) * L * ncol, s, a);
+            hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(256), lds, s, a);
             KP_LAUNCH_CHECK();
         };
         if (!inverse)
