@@ -217,7 +217,7 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
         ssp[i + 1] = ssp[i] + P.nwork;
         maxL = std::max(maxL, std::max(P.G[0], P.G[1]));
         spread_thr = std::max(spread_thr, ((spread_threads(2, P.Bs, C) + 63) / 64) * 64);
-        spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C));
+        spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C, kZMax));
     }
     const int nh = (int)hv.size();
     const DescLayout L = desc_layout(n, K, nh);

@@ -591,17 +591,23 @@ int spread_threads(int d, const int* B, int C) {
 }
 
 // LDS carve-up for a chunk of E entries (all 4-byte words):
-//   code[E] | wl[(d-1) W][E] | wz[kZMax][E] | u[C][E] (float2) | bstart[NBK+1]
+//   code[E] | wl[(d-1) W][E+1] | wz[ZM][E] | u[C][E+1] (float2) | bstart[NBK+1]
+// (rows of wl and u padded by one element: lanes reading one entry from
+// different rows, or different coil groups, fall into different banks)
 // (entry index fastest, so lanes reading different entries hit different banks)
 // buckets of a tile: first-tap positions -(W-1) .. B_a - 1 on the leading axes
 int spread_nbk(int d, int W, const int* B) {
     return d == 3 ? (B[0] + W - 1) * (B[1] + W - 1) : (B[0] + W - 1);
 }
 
-size_t spread_lds_bytes(int d, int W, const int* B, int C) {
-    const size_t E = kSpreadChunk;
+// register line length of the spreading kernel for a tile depth
+int spread_zm(int d, const int* B) { return B[d - 1] <= 4 ? 4 : kZMax; }
+
+size_t spread_lds_bytes(int d, int W, const int* B, int C, int zm) {
+    const size_t E = kSpreadChunk, EP = E + 1;
     const size_t nbk = (size_t)spread_nbk(d, W, B);
-    const size_t words = E * (1 + (size_t)(d - 1) * W + kZMax + 2 * (size_t)C) + nbk + 1;
+    if (zm <= 0) zm = spread_zm(d, B);
+    const size_t words = E + EP * (size_t)(d - 1) * W + E * (size_t)zm + 2 * EP * (size_t)C + nbk + 1;
     return 4 * words;
 }
 
@@ -621,11 +627,12 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
     const int ZL = a.B[D - 1];
     const int NB1 = D == 3 ? B1 + W - 1 : 1;
     const int NBK = D == 3 ? (B0 + W - 1) * NB1 : (B0 + W - 1);
+    constexpr int EP = E + 1;
     int* code = smem;
     float* wl = (float*)(code + E);
-    float* wz = wl + E * NLW;
-    float2* uu = (float2*)(wz + E * kZMax);
-    int* bstart = (int*)(uu + E * C);
+    float* wz = wl + EP * NLW;
+    float2* uu = (float2*)(wz + E * ZM);
+    int* bstart = (int*)(uu + EP * C);
 
     const int4 wk = a.work[item];
     const int tile = wk.x, start = wk.y, count = wk.z, slot = wk.w;
@@ -669,7 +676,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
                 tap_weights<W>(g - cf, kb, w);
                 if (ax < D - 1) {
 #pragma unroll
-                    for (int t = 0; t < W; ++t) wl[(ax * W + t) * E + e] = w[t];
+                    for (int t = 0; t < W; ++t) wl[(ax * W + t) * EP + e] = w[t];
                 } else {
                     int l = (int)cf - W / 2 + 1 - org[ax];
                     if (l < -(W - 1)) l += a.G[ax];
@@ -687,7 +694,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
             // low 16 bits: bucket; high bits: its axis-1 coordinate (3D)
             code[e] = bk | ((D == 3 ? bk % NB1 : 0) << 16);
             const float2* src = a.k + (int64_t)s * C;
-            for (int c = 0; c < C; ++c) uu[c * E + e] = src[c];
+            for (int c = 0; c < C; ++c) uu[c * EP + e] = src[c];
         }
         __syncthreads();
         // ---- B: first entry of every bucket (the chunk is sorted by bucket)
@@ -706,12 +713,12 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
             // entries form one contiguous run; the axis-1 tap of an entry
             // follows from its bucket coordinate b1
             auto gather = [&](int idx, int t0) {
-                float wA = wl[t0 * E + idx];
-                if (D == 3) wA *= wl[(W + j1 + W - 1 - (code[idx] >> 16)) * E + idx];
-                const float2* up = uu + (cg * CG) * E + idx;
+                float wA = wl[t0 * EP + idx];
+                if (D == 3) wA *= wl[(W + j1 + W - 1 - (code[idx] >> 16)) * EP + idx];
+                const float2* up = uu + (cg * CG) * EP + idx;
                 float2 uv[CG];
 #pragma unroll
-                for (int c = 0; c < CG; ++c) uv[c] = up[c * E];
+                for (int c = 0; c < CG; ++c) uv[c] = up[c * EP];
 #pragma unroll
                 for (int z = 0; z < ZM; ++z) {
                     const float wt = wA * wz[z * E + idx];
@@ -892,11 +899,11 @@ static void spread_dispatch_z(const SpreadArgs& a, const KbParams& kb, size_t ld
 // tiles at most 4 cells deep along the last axis keep 4-cell register lines
 template <int D, int W>
 static void spread_dispatch(const SpreadArgs& a, const KbParams& kb, hipStream_t s) {
-    const size_t lds = spread_lds_bytes(D, W, a.B, a.C);
+    const size_t lds = spread_lds_bytes(D, W, a.B, a.C, spread_zm(D, a.B));
     const int nthr = spread_threads(D, a.B, a.C);
     const int block = ((nthr + 63) / 64) * 64;
     if (block > 256) fail(KP_ERR_UNSUPPORTED, "spreading tile needs more than 256 threads");
-    if (a.B[D - 1] <= 4)
+    if (spread_zm(D, a.B) == 4)
         spread_dispatch_z<D, W, 4>(a, kb, lds, block, s);
     else
         spread_dispatch_z<D, W, kZMax>(a, kb, lds, block, s);

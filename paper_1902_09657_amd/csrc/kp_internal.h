@@ -159,7 +159,8 @@ constexpr int kSpreadChunk = 128;   // touch entries staged in LDS at a time
 constexpr int kZMax = 8;            // tile extent along the last axis (max)
 int spread_threads(int d, const int* B, int C);
 int spread_nbk(int d, int W, const int* B);
-size_t spread_lds_bytes(int d, int W, const int* B, int C);
+int spread_zm(int d, const int* B);
+size_t spread_lds_bytes(int d, int W, const int* B, int C, int zm = 0);
 
 void launch_interp(int d, int W, const InterpArgs& a, const KbParams& kb, hipStream_t s);
 // tile-staged interpolation over pieces (tile, first sorted sample, count, 0)
