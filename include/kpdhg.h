@@ -222,8 +222,11 @@ int nufft_plan_validate(int ndim, const int64_t* shape, int64_t ncoils, int64_t 
  *   KP_STAGE_FWD_FFT  pre-pass + pruned forward FFT passes (d kernels)
  *   KP_STAGE_INTERP   Kaiser-Bessel interpolation into internal k-space
  *   KP_STAGE_SPREAD   tile spreading of internal k-space onto the grid
- *   KP_STAGE_ADJ_FFT  pruned inverse FFT passes + post-pass (d kernels) */
-enum { KP_STAGE_FWD_FFT = 0, KP_STAGE_INTERP = 1, KP_STAGE_SPREAD = 2, KP_STAGE_ADJ_FFT = 3 };
+ *   KP_STAGE_ADJ_FFT  pruned inverse FFT passes + post-pass (d kernels)
+ *   KP_STAGE_SPREAD_TILES  the tile kernel of KP_STAGE_SPREAD alone (split
+ *                     tiles left as unreduced partial tiles) */
+enum { KP_STAGE_FWD_FFT = 0, KP_STAGE_INTERP = 1, KP_STAGE_SPREAD = 2, KP_STAGE_ADJ_FFT = 3,
+       KP_STAGE_SPREAD_TILES = 4 };
 int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream);
 
 /* ---------------------------------------------------------------- batches
