@@ -1,0 +1,178 @@
+"""GPU parity at the full sizes of the benchmark workloads.
+
+* 2D radial 128^2 (1 coil, SC, l2, 20 iterations) and 2D spiral 256^2 (8 coils,
+  MC, l1-db4, 30 iterations): the whole solve against the oracle.
+* 3D UTE 160^3, 8 coils, 2.56 M samples/coil (the timed workload, same plan as
+  the benchmark): the full forward and adjoint against the oracle, the adjoint
+  identity, and the first two PDHG iterations against the oracle (P = I and a
+  fixed lambda_max keep the oracle's cost to four NUFFTs per iteration).
+* Slices of the 64-slice batched workload, solved as one batch, against the
+  oracle slice by slice.
+* The differentiable workload's slice size (256^2, 12 coils, 24 x 2048 spiral):
+  unrolled forward and gradients against the oracle's reverse recursion.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import nufft as onufft
+from oracle import pdhg as opdhg
+from oracle import precond as oprecond
+from oracle import unrolled as ounrolled
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+
+def _kp():
+    import paper_1902_09657_amd as kp
+    return kp
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _plan(kp, k, shape, maps, alpha, W):
+    m = None if maps is None else dev(maps, torch.complex64)
+    return kp.nufft_plan(dev(k, torch.float32), shape, m, oversamp=alpha, kb_width=W)
+
+
+@pytest.mark.parametrize("cfg_id", [1, 2])
+def test_2d_workload_full_solve(cfg_id):
+    kp = _kp()
+    cfg = synth.config(cfg_id)
+    print("full solve", cfg.name, flush=True)
+    x, maps, k, w = cfg.inputs(seed=cfg_id)
+    op = onufft.Nufft(k, cfg.shape, maps, cfg.alpha, cfg.width)
+    y = op.forward(x) + w
+    if cfg.precond == "sc":
+        p = oprecond.efficient_nufft(None, k, cfg.shape, cfg.alpha, cfg.width)[0]
+    else:
+        p = oprecond.efficient_nufft(maps, k, cfg.shape, cfg.alpha, cfg.width)
+    hist = []
+    xo, _, _ = opdhg.pdhg(op.forward, op.adjoint, y, p, cfg.shape, cfg.reg, cfg.lam, cfg.iters, levels=4,
+                          history=hist)
+    plan = _plan(kp, k, cfg.shape, maps, cfg.alpha, cfg.width)
+    pg = kp.precond_build(plan, kp.KP_PRECOND_SC if cfg.precond == "sc" else kp.KP_PRECOND_MC).cpu().numpy()
+    assert rel(pg, p) < 1e-4
+    xg, hg = kp.pdhg_solve(plan, dev(y, torch.complex64), dev(p, torch.float32), reg=cfg.reg, lam=cfg.lam,
+                           iters=cfg.iters, wavelet_levels=4, objective=True)
+    print("x rel", rel(xg.cpu().numpy(), xo), flush=True)
+    assert rel(xg.cpu().numpy(), xo) < 1e-4
+    np.testing.assert_allclose(hg, hist, rtol=1e-4)
+    assert hg[-1] < hg[0]
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def ute():
+    """The timed 3D workload: inputs, the oracle operator and the GPU plan."""
+    kp = _kp()
+    cfg = synth.config(3)
+    x, maps, k, w = cfg.inputs(seed=3)
+    print("3D UTE: oracle taps", flush=True)
+    op = onufft.Nufft(k, cfg.shape, maps, cfg.alpha, cfg.width)
+    plan = _plan(kp, k, cfg.shape, maps, cfg.alpha, cfg.width)
+    yield kp, cfg, x, maps, k, w, op, plan
+    plan.close()
+
+
+def test_3d_ute_forward_adjoint_full(ute):
+    kp, cfg, x, maps, k, w, op, plan = ute
+    print("3D UTE forward", flush=True)
+    yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
+    yo = op.forward(x)
+    assert rel(yg, yo) < 1e-4
+    print("3D UTE adjoint", flush=True)
+    rng = np.random.default_rng(31)
+    y = (rng.standard_normal(yo.shape) + 1j * rng.standard_normal(yo.shape)) / np.sqrt(2.0)
+    xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
+    assert rel(xg, op.adjoint(y)) < 1e-4
+
+
+def test_3d_ute_adjoint_identity(ute):
+    kp, cfg, x, maps, k, w, op, plan = ute
+    rng = np.random.default_rng(32)
+    xt = dev(x, torch.complex64)
+    yt = dev(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape), torch.complex64)
+    ax = kp.nufft_forward(plan, xt)
+    ahy = kp.nufft_adjoint(plan, yt)
+    lhs = torch.vdot(ax.flatten().to(torch.complex128), yt.flatten().to(torch.complex128)).item()
+    rhs = torch.vdot(xt.flatten().to(torch.complex128), ahy.flatten().to(torch.complex128)).item()
+    assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
+
+
+def test_3d_ute_pdhg_first_iterations(ute):
+    kp, cfg, x, maps, k, w, op, plan = ute
+    print("3D UTE two PDHG iterations", flush=True)
+    y = op.forward(x) + w
+    lmax = 2.0
+    xo, uo, _ = opdhg.pdhg(op.forward, op.adjoint, y, None, cfg.shape, "l1wav", cfg.lam, 2, lmax=lmax, levels=4)
+    xg, ug = kp.pdhg_solve(plan, dev(y, torch.complex64), None, reg="l1wav", lam=cfg.lam, iters=2,
+                           wavelet_levels=4, lambda_max=lmax, want_u=True)
+    assert rel(xg.cpu().numpy(), xo) < 1e-4
+    assert rel(ug.cpu().numpy(), uo) < 1e-4
+
+
+def test_batched_workload_slices():
+    """Three slices of the 64-slice set (the two first of size 128 and the
+    first of size 192), 12 coils, SC preconditioner, l2, 20 iterations."""
+    kp = _kp()
+    sl = synth.slice_config4(64, seed=4, ncoils=12)
+    pick = [i for i, (s, _) in enumerate(sl) if s[0] == 128][:2] + [i for i, (s, _) in enumerate(sl) if s[0] == 192][:1]
+    coords, maps_l, ys, ps, ops = [], [], [], [], []
+    for i in pick:
+        shape, k = sl[i]
+        rp, rm, _, rn = synth.streams(4000 + i)
+        x = synth.phantom(shape, rp)
+        m = synth.coil_maps(shape, 12, rm)
+        op = onufft.Nufft(k, shape, m, 1.25, 4)
+        ys.append(op.forward(x) + synth.noise((12, k.shape[0]), 1e-3, rn))
+        ps.append(oprecond.efficient_nufft(None, k, shape, 1.25, 4)[0])
+        coords.append(dev(k, torch.float32))
+        maps_l.append(dev(m, torch.complex64))
+        ops.append(op)
+    print("batched slices", pick, [sl[i][0] for i in pick], flush=True)
+    b = kp.nufft_plan_batch(coords, [sl[i][0] for i in pick], maps_l, oversamp=1.25, kb_width=4, tune=True)
+    assert all(kp.nufft_batch_info(b, j)["fast"] for j in range(len(pick)))
+    lm = [1.5] * len(pick)
+    xb = kp.pdhg_solve_batch(b, [dev(y, torch.complex64) for y in ys], [dev(p, torch.float32) for p in ps],
+                             lam=1e-3, iters=20, lambda_max=lm)
+    for j, i in enumerate(pick):
+        xo, _, _ = opdhg.pdhg(ops[j].forward, ops[j].adjoint, ys[j], ps[j], sl[i][0], "l2", 1e-3, 20, lmax=lm[j])
+        r = rel(xb[j].cpu().numpy(), xo)
+        print("slice", i, sl[i][0], "rel", r, flush=True)
+        assert r < 1e-4
+    b.close()
+
+
+def test_differentiable_workload_slice():
+    from paper_1902_09657_amd.autograd import UnrolledPdhg, schedule_params
+    kp = _kp()
+    cfg = synth.config(5)
+    x, maps, k, w = cfg.inputs(seed=5000)
+    print("unrolled", cfg.name, flush=True)
+    op = onufft.Nufft(k, cfg.shape, maps, cfg.alpha, cfg.width)
+    y = op.forward(x) + w
+    p = oprecond.efficient_nufft(maps, k, cfg.shape, cfg.alpha, cfg.width)
+    K, lmax = cfg.iters, 1.8
+    sig, tau, th = opdhg.schedule(lmax, float(p.min()), K)
+    xK, rec = ounrolled.forward(op.forward, op.adjoint, y, p, sig, tau, th, cfg.lam, cfg.shape)
+    g = ounrolled.backward(op.forward, op.adjoint, y, p, sig, tau, th, cfg.lam, rec, xK - x)
+    plan = _plan(kp, k, cfg.shape, maps, cfg.alpha, cfg.width)
+    pt = dev(p, torch.float32)
+    params = schedule_params(plan, pt, K, lam=cfg.lam, lambda_max=lmax).requires_grad_(True)
+    xg = UnrolledPdhg.apply(dev(y, torch.complex64), params, plan, pt, K, 4, None)
+    assert rel(xg.detach().cpu().numpy(), xK) < 1e-4
+    r = xg - dev(x, torch.complex64)
+    (0.5 * (r.real ** 2 + r.imag ** 2).sum()).backward()
+    want = np.concatenate([g["sigma"], g["tau"], g["theta"], [g["lam"]]])
+    assert rel(params.grad.cpu().numpy(), want) < 1e-3
+    plan.close()
