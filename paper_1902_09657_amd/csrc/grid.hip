@@ -617,7 +617,10 @@ size_t spread_lds_bytes(int d, int W, const int* B, int C, int zm) {
 // Entries arrive in chunks of E, already ordered by the bucket of their first
 // tap on the leading axes (plan time), so the entries that reach a line form
 // W contiguous runs of the chunk; a binary search per bucket finds them.
-template <int D, int W, int CG, int ZM = kZMax>
+// PF: one entry per thread per chunk (blockDim >= E) and C <= 8; the
+// coordinates and coil values of the next chunk, and the touch indices of the
+// one after, are loaded while the current chunk is gathered.
+template <int D, int W, int CG, int ZM = kZMax, bool PF = false>
 __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams& kb, int64_t item, int* smem) {
     constexpr int E = kSpreadChunk;
     constexpr int NLW = (D - 1) * W;  // leading-axis weights per entry
@@ -661,40 +664,78 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
 #pragma unroll
         for (int c = 0; c < CG; ++c) acc[z][c] = make_float2(0.f, 0.f);
 
+    // weights and bucket of entry e into LDS (and its coil values when given)
+    auto stage = [&](int e, int bk, const float* gv, const float2* uv) {
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            const float g = gv[ax];
+            const float cf = floorf(g);
+            float w[W];
+            tap_weights<W>(g - cf, kb, w);
+            if (ax < D - 1) {
+#pragma unroll
+                for (int t = 0; t < W; ++t) wl[(ax * W + t) * EP + e] = w[t];
+            } else {
+                int l = (int)cf - W / 2 + 1 - org[ax];
+                if (l < -(W - 1)) l += a.G[ax];
+                else if (l > a.B[ax] - 1) l -= a.G[ax];
+#pragma unroll
+                for (int z = 0; z < ZM; ++z) {
+                    const int t = z - l;
+                    float v = 0.f;
+#pragma unroll
+                    for (int q = 0; q < W; ++q) v = (t == q) ? w[q] : v;
+                    wz[z * E + e] = (z < ZL) ? v : 0.f;
+                }
+            }
+        }
+        // low 16 bits: bucket; high bits: its axis-1 coordinate (3D)
+        code[e] = bk | ((D == 3 ? bk % NB1 : 0) << 16);
+        if (uv) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < C) uu[c * EP + e] = uv[c];
+        }
+    };
+    // pipeline registers (PF): data of the current chunk's entry tid, touch
+    // index and bucket of the next chunk's
+    int bk0 = 0, s1 = 0, bk1 = 0;
+    float g0[D];
+    float2 u0[8];
+    auto fetch = [&](int s) {
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) g0[ax] = a.g[(int64_t)s * D + ax];
+        const float2* src = a.k + (int64_t)s * C;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) u0[c] = c < C ? src[c] : make_float2(0.f, 0.f);
+    };
+    if (PF) {
+        if (tid < count) {
+            bk0 = a.code[start + tid];
+            fetch(a.touch[start + tid]);
+        }
+        if (E + tid < count) {
+            s1 = a.touch[start + E + tid];
+            bk1 = a.code[start + E + tid];
+        }
+    }
+
     for (int c0 = 0; c0 < count; c0 += E) {
         const int n = min(E, count - c0);
         if (c0 > 0) __syncthreads();  // the previous chunk is consumed
         // ---- A: stage the chunk: bucket, weights, coil values
-        for (int e = tid; e < n; e += blockDim.x) {
-            const int s = a.touch[start + c0 + e];
-            const int bk = a.code[start + c0 + e];
+        if (PF) {
+            if (tid < n) stage(tid, bk0, g0, u0);
+        } else {
+            for (int e = tid; e < n; e += blockDim.x) {
+                const int s = a.touch[start + c0 + e];
+                float gv[D];
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                const float g = a.g[(int64_t)s * D + ax];
-                const float cf = floorf(g);
-                float w[W];
-                tap_weights<W>(g - cf, kb, w);
-                if (ax < D - 1) {
-#pragma unroll
-                    for (int t = 0; t < W; ++t) wl[(ax * W + t) * EP + e] = w[t];
-                } else {
-                    int l = (int)cf - W / 2 + 1 - org[ax];
-                    if (l < -(W - 1)) l += a.G[ax];
-                    else if (l > a.B[ax] - 1) l -= a.G[ax];
-#pragma unroll
-                    for (int z = 0; z < ZM; ++z) {
-                        const int t = z - l;
-                        float v = 0.f;
-#pragma unroll
-                        for (int q = 0; q < W; ++q) v = (t == q) ? w[q] : v;
-                        wz[z * E + e] = (z < ZL) ? v : 0.f;
-                    }
-                }
+                for (int ax = 0; ax < D; ++ax) gv[ax] = a.g[(int64_t)s * D + ax];
+                const float2* src = a.k + (int64_t)s * C;
+                for (int c = 0; c < C; ++c) uu[c * EP + e] = src[c];
+                stage(e, a.code[start + c0 + e], gv, nullptr);
             }
-            // low 16 bits: bucket; high bits: its axis-1 coordinate (3D)
-            code[e] = bk | ((D == 3 ? bk % NB1 : 0) << 16);
-            const float2* src = a.k + (int64_t)s * C;
-            for (int c = 0; c < C; ++c) uu[c * EP + e] = src[c];
         }
         __syncthreads();
         // ---- B: first entry of every bucket (the chunk is sorted by bucket)
@@ -707,6 +748,16 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
             bstart[b] = lo;
         }
         __syncthreads();
+        if (PF) {  // loads for the next chunks, in flight during the gather
+            if (c0 + E + tid < count) {
+                bk0 = bk1;
+                fetch(s1);
+            }
+            if (c0 + 2 * E + tid < count) {
+                s1 = a.touch[start + c0 + 2 * E + tid];
+                bk1 = a.code[start + c0 + 2 * E + tid];
+            }
+        }
         // ---- C: each owner thread gathers the entries covering its line
         if (owner) {
             // the W buckets of one q0 along axis 1 are consecutive, so their
@@ -818,10 +869,10 @@ void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, 
     KP_LAUNCH_CHECK();
 }
 
-template <int D, int W, int CG, int ZM>
+template <int D, int W, int CG, int ZM, bool PF>
 __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
     extern __shared__ int smem[];
-    spread_body<D, W, CG, ZM>(a, kb, blockIdx.x, smem);
+    spread_body<D, W, CG, ZM, PF>(a, kb, blockIdx.x, smem);
 }
 
 // spreading of many slices in one launch (2D, width 4, coil groups of 4): the
@@ -880,20 +931,30 @@ void launch_reduce_batch(const SpreadArgs* d_args, const int2* d_hv, const int4*
     KP_LAUNCH_CHECK();
 }
 
+template <int D, int W, int CG, int ZM>
+static void spread_launch(const SpreadArgs& a, const KbParams& kb, size_t lds, int block, hipStream_t s) {
+    const dim3 grid((unsigned)a.nwork);
+    if (block >= kSpreadChunk && a.C <= 8) {
+        (void)hipFuncSetAttribute((const void*)k_spread<D, W, CG, ZM, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_spread<D, W, CG, ZM, true>), grid, dim3(block), lds, s, a, kb);
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_spread<D, W, CG, ZM, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_spread<D, W, CG, ZM, false>), grid, dim3(block), lds, s, a, kb);
+    }
+    KP_LAUNCH_CHECK();
+}
+
 template <int D, int W, int ZM>
 static void spread_dispatch_z(const SpreadArgs& a, const KbParams& kb, size_t lds, int block, hipStream_t s) {
     const int CG = coil_group(a.C);
-    const dim3 grid((unsigned)a.nwork);
-    const void* fn = CG == 4 ? (const void*)k_spread<D, W, 4, ZM>
-                             : (CG == 2 ? (const void*)k_spread<D, W, 2, ZM> : (const void*)k_spread<D, W, 1, ZM>);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (CG == 4)
-        hipLaunchKernelGGL((k_spread<D, W, 4, ZM>), grid, dim3(block), lds, s, a, kb);
+        spread_launch<D, W, 4, ZM>(a, kb, lds, block, s);
     else if (CG == 2)
-        hipLaunchKernelGGL((k_spread<D, W, 2, ZM>), grid, dim3(block), lds, s, a, kb);
+        spread_launch<D, W, 2, ZM>(a, kb, lds, block, s);
     else
-        hipLaunchKernelGGL((k_spread<D, W, 1, ZM>), grid, dim3(block), lds, s, a, kb);
-    KP_LAUNCH_CHECK();
+        spread_launch<D, W, 1, ZM>(a, kb, lds, block, s);
 }
 
 // tiles at most 4 cells deep along the last axis keep 4-cell register lines
