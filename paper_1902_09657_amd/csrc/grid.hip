@@ -389,7 +389,21 @@ __host__ __device__ inline int tl_h2p(int H2) { return H2 + ((12 - H2 % 8) % 8);
 __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
     extern __shared__ float4 tl_smem[];
     const int ncg = a.C / 4;
-    const int item = blockIdx.x / ncg, cg = blockIdx.x % ncg;
+    // The coil groups of one piece are launched 8 blocks apart (blocks are
+    // dealt to the 8 XCDs in turn, so they tend to share an L2 and the second
+    // half of every 64-byte grid cell is found there).
+    int item, cg;
+    {
+        const int b = blockIdx.x, nitems = gridDim.x / ncg;
+        const int grp = b / (8 * ncg), r = b % (8 * ncg);
+        if ((grp + 1) * 8 <= nitems) {
+            item = grp * 8 + r % 8;
+            cg = r / 8;
+        } else {
+            item = grp * 8 + r / ncg;
+            cg = r % ncg;
+        }
+    }
     const int4 wk = items[item];
     const int tile = wk.x, start = wk.y, count = wk.z;
     int org[3];
