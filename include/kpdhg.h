@@ -49,7 +49,7 @@ enum {
 };
 
 enum { KP_PRECOND_NONE = 0, KP_PRECOND_SC = 1, KP_PRECOND_MC = 2 };
-enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1 };
+enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1, KP_REG_TV = 2 };
 
 /* Kernel tiling.  Zeros select the built-in choice for the shape.
  * Samples are sorted by the tile (bin_size) that holds their grid cell; the
@@ -82,7 +82,7 @@ typedef struct {
 
 /* PDHG options (host struct). */
 typedef struct {
-    int reg;              /* KP_REG_L2 or KP_REG_L1_WAVELET                          */
+    int reg;              /* KP_REG_L2, KP_REG_L1_WAVELET or KP_REG_TV               */
     float lambda;         /* regularisation weight (Problem Setup, Eq. obj)          */
     int iters;            /* PDHG iterations K >= 1                                  */
     int wavelet_levels;   /* db4 levels for KP_REG_L1_WAVELET (every N_a % 2^L == 0) */
@@ -157,8 +157,17 @@ int pdhg_lambda_max(kp_plan_t plan, const float* p, int p_kind, int iters,
  * accelerated schedule theta_k = 1/(1 + 2 sigma_k min p), sigma_{k+1} =
  * theta_k sigma_k, tau_{k+1} = tau_k/theta_k (or theta = 1 if !accel).
  * g = lambda||x||^2/2 (prox z/(1+tau lambda)) or lambda||W x||_1 with the
- * periodised db4 W (prox W^H soft(W z, tau lambda)).  x0 = u0 = 0 unless
- * given.  y: c64 [C][M]; p: NULL / float [M] / float [C][M] per p_kind;
+ * periodised db4 W (prox W^H soft(W z, tau lambda)).
+ * KP_REG_TV, g = lambda ||G x||_1 with G the periodic forward differences
+ * along every axis (anisotropic, complex modulus per component), follows
+ * "Preconditioned PDHG for simple regularizers composed with linear
+ * operators": a second dual v for G x,
+ *   v  <- clip_lambda(v + sigma G xbar)   (prox of sigma h*, h = lambda||.||_1)
+ *   x' <- x - tau (A^H u + G^H v)
+ * with constant steps sigma = theta = 1, tau = 1/(lambda_max + lambda_max(G G^H)),
+ * lambda_max(G G^H) = 4 d (every N_a is even); opts->sigma0 and accel are
+ * not used.  x0 = u0 = 0 (and v = 0) unless given.
+ * y: c64 [C][M]; p: NULL / float [M] / float [C][M] per p_kind;
  * x_out: c64 [N]; u_out: NULL or c64 [C][M] (caller order).  No host sync
  * unless opts->objective_host is set. */
 int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind,

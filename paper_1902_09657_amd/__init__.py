@@ -12,14 +12,14 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVELET, KP_REG_L2,
+from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVELET, KP_REG_L2, KP_REG_TV,
                    KpError, PdhgOpts, PlanInfo, Tuning)
 
 __all__ = [
     "Plan", "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
     "pdhg_solve", "nufft_destroy", "nufft_autotune", "Batch", "nufft_plan_batch", "nufft_batch_info",
     "pdhg_solve_batch", "nufft_batch_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
-    "KP_REG_L2", "KP_REG_L1_WAVELET",
+    "KP_REG_L2", "KP_REG_L1_WAVELET", "KP_REG_TV",
 ]
 
 
@@ -163,12 +163,16 @@ def pdhg_lambda_max(plan: Plan, p=None, iters=30):
 def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_levels=4, lambda_max=0.0,
                power_iters=30, sigma0=1.0, accel=True, x0=None, u0=None, objective=False, want_u=False,
                lambda_max_out=None):
-    """Run the preconditioned PDHG.  Returns x (and u, objective history when asked)."""
+    """Run the preconditioned PDHG (reg "l2", "l1wav" or "tv").  Returns x (and u,
+    objective history when asked)."""
     y = _dev(y, torch.complex64, "y")
     if p is not None:
         p = _dev(p, torch.float32, "p")
     o = PdhgOpts()
-    o.reg = KP_REG_L2 if reg == "l2" else KP_REG_L1_WAVELET
+    regs = {"l2": KP_REG_L2, "l1wav": KP_REG_L1_WAVELET, "tv": KP_REG_TV}
+    if reg not in regs:
+        raise ValueError("reg must be one of %s" % sorted(regs))
+    o.reg = regs[reg]
     o.lam = float(lam)
     o.iters = int(iters)
     o.wavelet_levels = int(wavelet_levels)

@@ -216,6 +216,7 @@ struct Plan {
     DevBuf kint3;                 // third internal k-space (residuals, gradients)
     DevBuf pint;                  // internal preconditioner [M][C]
     DevBuf img[4];                // image workspaces [N]
+    DevBuf tvv;                   // TV dual variable [d][N]
     DevBuf red;                   // reduction scratch
     DevBuf sched;                 // schedule arrays
     std::vector<int> fft_nst[3];

@@ -402,6 +402,112 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
         for (int l = levels - 1; l >= 0; --l) run_level(l);
 }
 
+// ------------------------------------------------------------- total variation
+// G: periodic forward differences along every axis, (G x)_a[n] = x[n + e_a] - x[n];
+// G^H v = sum_a v_a[n - e_a] - v_a[n].  The dual variable is stored [d][N].
+struct TvGeom {
+    int d;
+    int N[3];
+    int S[3];  // element strides
+};
+
+static TvGeom tv_geom(const Plan& P) {
+    TvGeom g{};
+    g.d = P.d;
+    int st = 1;
+    for (int a = P.d - 1; a >= 0; --a) {
+        g.N[a] = (int)P.N[a];
+        g.S[a] = st;
+        st *= (int)P.N[a];
+    }
+    return g;
+}
+
+__device__ __forceinline__ int tv_next(const TvGeom& g, int n, int a) {
+    const int c = (n / g.S[a]) % g.N[a];
+    return c == g.N[a] - 1 ? n - (g.N[a] - 1) * g.S[a] : n + g.S[a];
+}
+__device__ __forceinline__ int tv_prev(const TvGeom& g, int n, int a) {
+    const int c = (n / g.S[a]) % g.N[a];
+    return c == 0 ? n + (g.N[a] - 1) * g.S[a] : n - g.S[a];
+}
+
+// v <- clip_lambda(v + sigma G xbar), the prox of sigma h* for h = lambda ||.||_1
+__global__ void k_tv_dual(float2* v, const float2* xbar, TvGeom g, int n_tot, const float* sigma, float lam) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_tot) return;
+    const float sg = *sigma;
+    const float2 x0 = xbar[n];
+    for (int a = 0; a < g.d; ++a) {
+        const float2 x1 = xbar[tv_next(g, n, a)];
+        float2 w = v[(int64_t)a * n_tot + n];
+        w.x += sg * (x1.x - x0.x);
+        w.y += sg * (x1.y - x0.y);
+        const float mag = sqrtf(w.x * w.x + w.y * w.y);
+        if (mag > lam) {
+            const float f = lam / mag;
+            w.x *= f;
+            w.y *= f;
+        }
+        v[(int64_t)a * n_tot + n] = w;
+    }
+}
+
+// x' = z - tau G^H v with z = x - tau A^H u; xbar = x' + theta (x' - x); x = x'
+__global__ void k_tv_primal(const float2* z, const float2* v, float2* x, float2* xbar, TvGeom g, int n_tot,
+                            const float* tau, const float* theta) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_tot) return;
+    float2 gh = make_float2(0.f, 0.f);
+    for (int a = 0; a < g.d; ++a) {
+        const float2 vp = v[(int64_t)a * n_tot + tv_prev(g, n, a)];
+        const float2 vn = v[(int64_t)a * n_tot + n];
+        gh.x += vp.x - vn.x;
+        gh.y += vp.y - vn.y;
+    }
+    const float t = *tau, th = *theta;
+    const float2 zv = z[n], xo = x[n];
+    const float2 xn = make_float2(zv.x - t * gh.x, zv.y - t * gh.y);
+    xbar[n] = make_float2(xn.x + th * (xn.x - xo.x), xn.y + th * (xn.y - xo.y));
+    x[n] = xn;
+}
+
+// sum_n sum_a |(G x)_a[n]| (per-block partial sums in FP64)
+__global__ void k_red_tv(const float2* x, TvGeom g, int n_tot, double* part) {
+    double acc = 0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < n_tot; n += gridDim.x * blockDim.x) {
+        const float2 x0 = x[n];
+        for (int a = 0; a < g.d; ++a) {
+            const float2 x1 = x[tv_next(g, n, a)];
+            const double dx = (double)x1.x - x0.x, dy = (double)x1.y - x0.y;
+            acc += sqrt(dx * dx + dy * dy);
+        }
+    }
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// lambda_max(G G^H) = sum_a max_k 2 (1 - cos(2 pi k / N_a))
+static double tv_lmax(const Plan& P) {
+    double t = 0;
+    for (int a = 0; a < P.d; ++a) {
+        double m = 0;
+        for (int64_t k = 0; k < P.N[a]; ++k) m = std::max(m, 2.0 * (1.0 - std::cos(2.0 * M_PI * (double)k / (double)P.N[a])));
+        t += m;
+    }
+    return t;
+}
+
+// constant TV steps: sigma = theta = 1, tau = 1 / (lambda_max + lambda_max(G G^H))
+__global__ void k_schedule_tv(const float* lmax, double lgg, int K, float* sig, float* tau, float* th) {
+    const float t = (float)(1.0 / ((double)*lmax + lgg));
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        sig[k] = 1.f;
+        tau[k] = t;
+        th[k] = 1.f;
+    }
+}
+
 // ------------------------------------------------------------- operators
 // Apply A^H P A to v (power method step), result into `out`.
 static void normal_op(Plan& P, const float2* v, const float* xscale, const float* pint, int p_mc, float2* out,
@@ -453,6 +559,12 @@ static double objective(Plan& P, const float2* x, const float2* yint, int reg, f
     reduce(P.kint3.as<float2>(), yint, P.M * P.C, 1, acc, 0.5, false, part, s);
     if (reg == KP_REG_L2) {
         reduce(x, nullptr, P.Ntot, 0, acc, 0.5 * lam, true, part, s);
+    } else if (reg == KP_REG_TV) {
+        const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (P.Ntot + 255) / 256));
+        hipLaunchKernelGGL(k_red_tv, dim3(nb), dim3(256), 0, s, x, tv_geom(P), (int)P.Ntot, part);
+        KP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, part, nb, acc, (double)lam, 1);
+        KP_LAUNCH_CHECK();
     } else {
         float2* w = P.img[3].as<float2>();
         copy2(x, w, P.Ntot, s);
@@ -486,7 +598,12 @@ const float* load_p(Plan& P, const float* p, int p_kind, hipStream_t s) {
 void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, hipStream_t s) {
     check_p(P, p, p_kind);
     if (op.iters < 1 || op.iters > 8192) fail(KP_ERR_INVALID_ARG, "iters must lie in [1, 8192]");
-    if (op.reg != KP_REG_L2 && op.reg != KP_REG_L1_WAVELET) fail(KP_ERR_INVALID_ARG, "unknown regulariser");
+    if (op.reg != KP_REG_L2 && op.reg != KP_REG_L1_WAVELET && op.reg != KP_REG_TV)
+        fail(KP_ERR_INVALID_ARG, "unknown regulariser");
+    if (op.reg == KP_REG_TV) {
+        if (!P.tvv.p) fail(KP_ERR_UNSUPPORTED, "TV needs a plan with coil maps or one coil");
+        if (P.Ntot >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "TV: image too large");
+    }
     if (!(op.lambda >= 0.f)) fail(KP_ERR_INVALID_ARG, "lambda must be >= 0");
     if (!(op.sigma0 > 0.f)) fail(KP_ERR_INVALID_ARG, "sigma0 must be > 0");
     const int levels = op.wavelet_levels;
@@ -534,8 +651,13 @@ void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_p
     KP_LAUNCH_CHECK();
     if (op.lambda_max_out)
         KP_HIP(hipMemcpyAsync(op.lambda_max_out, slot(P, SL_LMAX), sizeof(float), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), slot(P, SL_PMIN), K, op.sigma0,
-                       op.accel, sig, tau, th);
+    if (op.reg == KP_REG_TV) {
+        hipLaunchKernelGGL(k_schedule_tv, dim3(1), dim3(256), 0, s, slot(P, SL_LMAX), tv_lmax(P), K, sig, tau, th);
+        fill2(P.tvv.as<float2>(), P.Ntot * P.d, 0.f, 0.f, s);
+    } else {
+        hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1), 0, s, slot(P, SL_LMAX), slot(P, SL_PMIN), K, op.sigma0,
+                           op.accel, sig, tau, th);
+    }
     KP_LAUNCH_CHECK();
 }
 
@@ -577,6 +699,19 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
             ao.epi = EPI_L2;
             ao.exbar = xbar;
             grid_to_image(P, g2, z, ao, s);
+        } else if (op.reg == KP_REG_TV) {
+            // the new v uses the xbar of this iteration: update it before x changes
+            const TvGeom tg = tv_geom(P);
+            float2* v = P.tvv.as<float2>();
+            hipLaunchKernelGGL(k_tv_dual, dim3(nblk(P.Ntot)), dim3(256), 0, s, v, xbar, tg, (int)P.Ntot, sig + k,
+                               op.lambda);
+            KP_LAUNCH_CHECK();
+            ao.epi = EPI_Z;
+            ao.exbar = z;
+            grid_to_image(P, g2, z, ao, s);
+            hipLaunchKernelGGL(k_tv_primal, dim3(nblk(P.Ntot)), dim3(256), 0, s, z, v, x, xbar, tg, (int)P.Ntot,
+                               tau + k, th + k);
+            KP_LAUNCH_CHECK();
         } else {
             ao.epi = EPI_Z;
             ao.exbar = z;

@@ -158,3 +158,38 @@ def test_pdhg_invalid_options():
             kp.pdhg_solve(plan, yt, None, **kw)
         assert ei.value.code == kp._lib.KP_ERR_INVALID_ARG
     plan.close()
+
+
+TV_CASES = [
+    # shape, C, M, precond, iters
+    ((32, 48), 4, 3000, "mc", 20),
+    ((40, 24), 1, 2500, "sc", 25),
+    ((16, 20, 24), 3, 4000, "none", 10),
+    ((16, 16, 16), 8, 5000, "mc", 8),
+]
+
+
+@pytest.mark.parametrize("shape,C,M,pk,iters", TV_CASES)
+def test_pdhg_tv_parity(shape, C, M, pk, iters):
+    from oracle import tv as otv
+    kp = _kp()
+    print("tv case", shape, C, M, pk, iters, flush=True)
+    k, maps, x, y, op = problem(shape, C, M, 7, 1.25, 4, "random")
+    plan = plan_for(kp, k, shape, maps, 1.25, 4)
+    if pk == "none":
+        p = None
+    elif pk == "sc":
+        p = oprecond.efficient_nufft(None, k, shape, 1.25, 4)[0]
+    else:
+        p = oprecond.efficient_nufft(maps, k, shape, 1.25, 4)
+    pt = None if p is None else dev(p, torch.float32)
+    lam = 5e-3
+    hist = []
+    xo, uo, _, _ = otv.tv_pdhg(op.forward, op.adjoint, y, p, shape, lam, iters, history=hist)
+    xg, ug, hg = kp.pdhg_solve(plan, dev(y, torch.complex64), pt, reg="tv", lam=lam, iters=iters, want_u=True,
+                               objective=True)
+    assert rel(xg.cpu().numpy(), xo) < 1e-4
+    assert rel(ug.cpu().numpy(), uo) < 1e-4
+    np.testing.assert_allclose(hg, hist, rtol=1e-4)
+    assert hg[-1] < hg[0]
+    plan.close()
