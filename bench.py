@@ -380,6 +380,16 @@ def main():
     t_solve = e0.elapsed_time(e1) / 1e3
     assert torch.isfinite(xr).all().item()
 
+    # the same workload with the TV regulariser (constant steps), timed alike
+    log("timed TV solve")
+    kp.pdhg_solve(plan, y, p, reg="tv", lam=cfg.lam, lambda_max=lmax_v, iters=2)
+    torch.cuda.synchronize()
+    e0.record(s)
+    kp.pdhg_solve(plan, y, p, reg="tv", lam=cfg.lam, lambda_max=lmax_v, iters=args.steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_tv = e0.elapsed_time(e1) / 1e3
+
     # plain NUFFT forward + adjoint pairs through the C ABI
     log("nufft pairs")
     xa = torch.empty_like(xt)
@@ -442,6 +452,7 @@ def main():
                    "oversamp": cfg.alpha, "kb_width": cfg.width, "reg": "l1-db4-4lev", "lambda": cfg.lam,
                    "precond": "mc", "iters": K},
         "pdhg_iters_per_s": round(K / t_solve, 2),
+        "tv_ms_per_step": round(t_tv / K * 1e3, 4),
         "nufft_pair_ms": round(t_pair * 1e3, 4),
         "nufft_pair_msamples_coil_per_s": round(M * C / t_pair / 1e6, 2),
         "nufft_pair_hbm_roofline_frac": round(bm["total"] / t_pair / 1e9 / HBM_PEAK_GBS, 4),

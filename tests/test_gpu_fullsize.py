@@ -1,7 +1,8 @@
 """GPU parity at the full sizes of the benchmark workloads.
 
 * 2D radial 128^2 (1 coil, SC, l2, 20 iterations) and 2D spiral 256^2 (8 coils,
-  MC, l1-db4, 30 iterations): the whole solve against the oracle.
+  MC, l1-db4, 30 iterations): the whole solve against the oracle; the spiral
+  workload also with the TV regulariser.
 * 3D UTE 160^3, 8 coils, 2.56 M samples/coil (the timed workload, same plan as
   the benchmark): the full forward and adjoint against the oracle, the adjoint
   identity, and the first two PDHG iterations against the oracle (P = I and a
@@ -68,6 +69,25 @@ def test_2d_workload_full_solve(cfg_id):
     assert rel(xg.cpu().numpy(), xo) < 1e-4
     np.testing.assert_allclose(hg, hist, rtol=1e-4)
     assert hg[-1] < hg[0]
+    plan.close()
+
+
+def test_2d_spiral_workload_tv_solve():
+    """The 2D spiral workload (256^2, 8 coils, MC) with the TV regulariser."""
+    from oracle import tv as otv
+    kp = _kp()
+    cfg = synth.config(2)
+    x, maps, k, w = cfg.inputs(seed=2)
+    op = onufft.Nufft(k, cfg.shape, maps, cfg.alpha, cfg.width)
+    y = op.forward(x) + w
+    p = oprecond.efficient_nufft(maps, k, cfg.shape, cfg.alpha, cfg.width)
+    hist = []
+    xo, _, _, _ = otv.tv_pdhg(op.forward, op.adjoint, y, p, cfg.shape, cfg.lam, cfg.iters, history=hist)
+    plan = _plan(kp, k, cfg.shape, maps, cfg.alpha, cfg.width)
+    xg, hg = kp.pdhg_solve(plan, dev(y, torch.complex64), dev(p, torch.float32), reg="tv", lam=cfg.lam,
+                           iters=cfg.iters, objective=True)
+    assert rel(xg.cpu().numpy(), xo) < 1e-4
+    np.testing.assert_allclose(hg, hist, rtol=1e-4)
     plan.close()
 
 
