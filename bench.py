@@ -283,6 +283,74 @@ def bench_differentiable(kp, dev, reps=3):
     }
 
 
+def bench_context(kp, dev):
+    """Context runs (not the headline): (1) P = I vs SC vs MC on the 2D spiral
+    workload (256^2, 8 coils, l1-db4, 30 iterations): normalised objective gap
+    (f_k - f*) / (f_0 - f*) with f* from 300 MC-preconditioned iterations, and
+    the time per iteration; (2) preconditioner build time at the two fully
+    specified shapes of the paper's Table I (synthetic trajectories and maps;
+    the 255 x 200 brain matrix is taken as 256 x 200 since image extents must be
+    even here), beside the paper's Titan Xp figures."""
+    import torch
+    import synth
+    out = {}
+    cfg = synth.config(2)
+    x, maps, k, w = cfg.inputs(seed=2)
+    kt = torch.from_numpy(k).to(dev)
+    mt = torch.from_numpy(maps.astype(np.complex64)).to(dev)
+    hi = kp.nufft_plan(kt, cfg.shape, mt, oversamp=2.0, kb_width=8)
+    y = kp.nufft_forward(hi, torch.from_numpy(x.astype(np.complex64)).to(dev)) + \
+        torch.from_numpy(w.astype(np.complex64)).to(dev)
+    hi.close()
+    plan = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
+    ps = {"none": None, "sc": kp.precond_build(plan, kp.KP_PRECOND_SC), "mc": kp.precond_build(plan, kp.KP_PRECOND_MC)}
+    _, ref = kp.pdhg_solve(plan, y, ps["mc"], reg=cfg.reg, lam=cfg.lam, iters=300, wavelet_levels=4, objective=True)
+    fstar = min(ref)
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    comp = {}
+    for name, p in ps.items():
+        _, hist = kp.pdhg_solve(plan, y, p, reg=cfg.reg, lam=cfg.lam, iters=30, wavelet_levels=4, objective=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        kp.pdhg_solve(plan, y, p, reg=cfg.reg, lam=cfg.lam, iters=30, wavelet_levels=4)
+        e1.record(s)
+        torch.cuda.synchronize()
+        gap = [(h - fstar) / (hist[0] - fstar) for h in hist]
+        comp[name] = {"gap_at": {str(i): float("%.4g" % gap[i]) for i in (5, 10, 20, 30)},
+                      "ms_per_iter_incl_power_method": round(e0.elapsed_time(e1) / 30, 4)}
+    plan.close()
+    out["precond_comparison"] = {"workload": cfg.name + ", l1-db4 lambda 5e-3, 30 iterations",
+                                 "reference": "f* = min objective of 300 MC iterations", "gap": comp}
+    # Table I shapes
+    rows = []
+    rng = np.random.default_rng(7)
+    th = 2 * np.pi * np.arange(754) / 754
+    r = np.pi * np.arange(256) / 256
+    brain = np.stack([np.outer(np.cos(th), r).ravel(), np.outer(np.sin(th), r).ravel()], axis=1).astype(np.float32)
+    for name, shape, coords, paper_s in (("cardiac", (320, 320), synth.spiral_2d(3, 3996, 320 / 6), 0.117),
+                                         ("brain", (256, 200), brain, 0.0334)):
+        m = torch.from_numpy(synth.coil_maps(shape, 8, rng).astype(np.complex64)).to(dev)
+        ct = torch.from_numpy(coords).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl = kp.nufft_plan(ct, shape, m, oversamp=1.25, kb_width=4)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        kp.precond_build(pl, kp.KP_PRECOND_MC)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kp.precond_build(pl, kp.KP_PRECOND_MC)
+        torch.cuda.synchronize()
+        t_mc = time.perf_counter() - t0
+        pl.close()
+        rows.append({"dataset_shape": name, "image": list(shape), "coils": 8, "samples": int(coords.shape[0]),
+                     "plan_ms": round(t_plan * 1e3, 2), "mc_precond_ms": round(t_mc * 1e3, 2),
+                     "paper_mc_precond_ms_titan_xp": paper_s * 1e3})
+    out["table1_precond_build"] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +537,7 @@ def main():
     if not args.no_forms:
         result["batched"] = bench_batched(kp, dev)
         result["differentiable"] = bench_differentiable(kp, dev)
+        result["context"] = bench_context(kp, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one coil)")
         result["cpu_baseline"] = cpu_baseline(cfg, k, x, maps)
