@@ -173,6 +173,18 @@ int pdhg_lambda_max(kp_plan_t plan, const float* p, int p_kind, int iters,
 int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind,
                const kp_pdhg_opts* opts, void* x_out, void* u_out, void* stream);
 
+/* l2-regularised reconstruction through its dual (Supporting Materials,
+ * connection to Trzasko et al.): conjugate gradients on
+ * (A A^H + lambda I) u = lambda y with the diagonal k-space preconditioner P
+ * as M^-1 (P = I for KP_PRECOND_NONE), u_0 = 0, `iters` iterations (one NUFFT
+ * pair each), then x = A^H u / lambda, the minimiser of
+ * 1/2 ||A x - y||^2 + lambda/2 ||x||^2.  y: c64 [C][M]; p: as pdhg_solve;
+ * x_out: c64 [N]; u_out: NULL or c64 [C][M] (caller order); residual_host:
+ * NULL or host double [iters+1] receiving ||r_k|| / ||r_0|| (one host sync
+ * per iteration when given).  lambda > 0. */
+int l2_dual_cg(kp_plan_t plan, const void* y, const float* p, int p_kind, float lambda,
+               int iters, void* x_out, void* u_out, double* residual_host, void* stream);
+
 /* Unrolled differentiable l2 PDHG (same iteration as pdhg_solve, with free
  * per-step sizes): params = device float [3K+1] = sigma[K], tau[K],
  * theta[K], lambda.  Forward: runs K steps from x0 (NULL = 0), u0 = 0,

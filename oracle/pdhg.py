@@ -34,11 +34,19 @@ the PDHG iterate u (which tends to A x* - y):
 The Supporting Materials write x = A^H u / lambda for their dual variable;
 with the PDHG sign, u* = A x* - y and x* = -A^H u* / lambda.
 
+l2 dual solver (Supporting Materials, connection to Trzasko et al.): the dual
+optimum of the l2 problem solves (A A^H + lambda I) u = lambda y and gives
+x = A^H u / lambda; `l2_dual_pcg` solves it by conjugate gradients with the
+k-space preconditioner P as M^-1.  (The Supplement's u is the negative of the
+PDHG iterate u; its printed relation A x = u + y reads A x = y - u in its own
+sign, which is what x = A^H u / lambda and the optimality condition give.)
+
 Pins: power method vs eigvalsh of the dense A^H P A; l2 PDHG converges to the
 CG solution of (A^H A + lambda I) x = A^H y; duality gap -> 0; the unitary
 special case (single coil, full Cartesian, p = 1) matches the closed-form
-proximal solutions; preconditioned runs end below the unpreconditioned run
-(tests/test_oracle_solver.py).
+proximal solutions; preconditioned runs end below the unpreconditioned run;
+the dual PCG reaches the primal CG solution with and without P, and P cuts
+the iterations it needs (tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 
@@ -149,3 +157,36 @@ def cg_l2(fwd, adj, y, shape, lam, tol=1e-13, maxiter=5000):
     b = adj(np.asarray(y, np.complex128)).ravel()
     x, info = cg(op, b, rtol=tol, atol=0.0, maxiter=maxiter)
     return x.reshape(shape), info
+
+
+def l2_dual_pcg(fwd, adj, y, p, shape, lam, iters, history=None):
+    """l2-regularised reconstruction through its dual (Supporting Materials,
+    connection to Trzasko et al.): the dual optimum solves
+    (A A^H + lam I) u = lam y, and x = A^H u / lam.  Solved with conjugate
+    gradients preconditioned by the diagonal k-space preconditioner P
+    (M^-1 = P; P = I when p is None), u_0 = 0.  Returns (x, u); `history`
+    receives the relative residual ||r_k|| / ||r_0|| before every iteration
+    and after the last."""
+    y = np.asarray(y, dtype=np.complex128)
+    P = np.ones(y.shape) if p is None else np.broadcast_to(np.asarray(p, np.float64), y.shape)
+    H = lambda v: fwd(adj(v)) + lam * v
+    u = np.zeros(y.shape, np.complex128)
+    r = lam * y
+    z = P * r
+    d = z.copy()
+    rz = float(np.vdot(r, z).real)
+    r0 = float(np.linalg.norm(r))
+    for _ in range(iters):
+        if history is not None:
+            history.append(float(np.linalg.norm(r)) / r0)
+        q = H(d)
+        alpha = rz / float(np.vdot(d, q).real)
+        u = u + alpha * d
+        r = r - alpha * q
+        z = P * r
+        rz_new = float(np.vdot(r, z).real)
+        d = z + (rz_new / rz) * d
+        rz = rz_new
+    if history is not None:
+        history.append(float(np.linalg.norm(r)) / r0)
+    return adj(u) / lam, u

@@ -17,7 +17,7 @@ from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVE
 
 __all__ = [
     "Plan", "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
-    "pdhg_solve", "nufft_destroy", "nufft_autotune", "Batch", "nufft_plan_batch", "nufft_batch_info",
+    "pdhg_solve", "l2_dual_cg", "nufft_destroy", "nufft_autotune", "Batch", "nufft_plan_batch", "nufft_batch_info",
     "pdhg_solve_batch", "nufft_batch_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
     "KP_REG_L2", "KP_REG_L1_WAVELET", "KP_REG_TV",
 ]
@@ -201,6 +201,25 @@ def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_leve
         out.append(u)
     if objective:
         out.append([hist[i] for i in range(iters + 1)])
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def l2_dual_cg(plan: Plan, y, p=None, lam=1e-3, iters=50, want_u=False, residuals=False):
+    """l2 reconstruction through its dual: preconditioned CG on (A A^H + lam I) u = lam y,
+    x = A^H u / lam.  Returns x (and u, relative residual history when asked)."""
+    y = _dev(y, torch.complex64, "y")
+    if p is not None:
+        p = _dev(p, torch.float32, "p")
+    x = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
+    u = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device) if want_u else None
+    hist = (ctypes.c_double * (int(iters) + 1))() if residuals else None
+    _lib.check(_lib.load().l2_dual_cg(plan.handle, _ptr(y), _ptr(p), _p_kind(p), float(lam), int(iters), _ptr(x),
+                                      _ptr(u), hist, _stream()))
+    out = [x]
+    if want_u:
+        out.append(u)
+    if residuals:
+        out.append([hist[i] for i in range(int(iters) + 1)])
     return out[0] if len(out) == 1 else tuple(out)
 
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "pdhg_solve", "pdhg_unrolled_ckpt_bytes", "pdhg_unrolled_forward", "pdhg_unrolled_backward",
     "nufft_destroy", "nufft_plan_info", "nufft_plan_sort", "nufft_plan_grid_coords",
     "kp_db4_filter", "nufft_plan_validate", "kp_last_error", "nufft_stage",
-    "pdhg_schedule_params", "nufft_autotune", "nufft_plan_batch", "nufft_batch_info", "pdhg_solve_batch", "nufft_batch_destroy",
+    "pdhg_schedule_params", "l2_dual_cg", "nufft_autotune", "nufft_plan_batch", "nufft_batch_info", "pdhg_solve_batch", "nufft_batch_destroy",
 ]
 KP_STAGE_FWD_FFT, KP_STAGE_INTERP, KP_STAGE_SPREAD, KP_STAGE_ADJ_FFT, KP_STAGE_SPREAD_TILES = 0, 1, 2, 3, 4
 
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "kp_last_error": (ctypes.c_char_p, []),
         "nufft_stage": (i32, [vp, i32, i32, vp]),
         "pdhg_schedule_params": (i32, [vp, vp, i32, P(PdhgOpts), vp, vp]),
+        "l2_dual_cg": (i32, [vp, vp, vp, i32, f32, i32, vp, vp, P(ctypes.c_double), vp]),
         "nufft_autotune": (i32, [i32, P(i64), i64, i64, vp, vp, f32, i32, P(Tuning), vp]),
         "nufft_plan_batch": (i32, [P(vp), i32, P(i64), P(i64), i64, P(vp), P(vp), f32, i32, i32, vp]),
         "nufft_batch_info": (i32, [vp, i32, P(PlanInfo), P(i32)]),

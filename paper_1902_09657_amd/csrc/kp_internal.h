@@ -214,6 +214,7 @@ struct Plan {
     DevBuf kint;                  // internal k-space [M][C]
     DevBuf kint2;                 // second internal k-space (y for the solver)
     DevBuf kint3;                 // third internal k-space (residuals, gradients)
+    DevBuf kint4;                 // fourth internal k-space (the dual solver's iterate)
     DevBuf pint;                  // internal preconditioner [M][C]
     DevBuf img[4];                // image workspaces [N]
     DevBuf tvv;                   // TV dual variable [d][N]

@@ -723,7 +723,10 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     P->kint3.alloc(sizeof(float2) * M * C);
     P->pint.alloc(sizeof(float) * M * C);
     for (auto& b : P->img) b.alloc(sizeof(float2) * P->Ntot * (channel_mode ? C : 1));
-    if (!channel_mode) P->tvv.alloc(sizeof(float2) * P->Ntot * ndim);
+    if (!channel_mode) {
+        P->tvv.alloc(sizeof(float2) * P->Ntot * ndim);
+        P->kint4.alloc(sizeof(float2) * M * C);
+    }
     P->red.alloc(sizeof(double) * 65536);
     P->sched.alloc(sizeof(float) * (3 * 8192 + 64));
     KP_HIP(hipStreamSynchronize(s));
@@ -731,7 +734,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     int64_t total = 0;
     for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->touch_off, &P->touch, &P->work,
                       &P->heavy_list, &P->maps, &P->fo_fwd, &P->fr_fwd, &P->bufA, &P->bufB, &P->kint, &P->kint2, &P->kint3,
-                      &P->pint, &P->red, &P->sched, &P->tvv})
+                      &P->pint, &P->red, &P->sched, &P->tvv, &P->kint4})
         total += (int64_t)b->bytes;
     for (auto& b : P->img) total += (int64_t)b.bytes;
     for (auto& b : P->tw) total += (int64_t)b.bytes;

@@ -729,6 +729,145 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
     if (u_out) permute_to_caller(u, u_out, P.perm.as<int32_t>(), P.M, C, s);
 }
 
+
+// ------------------------------------------------------------- l2 dual solver
+// Supporting Materials, connection to Trzasko et al.: the dual optimum of the
+// l2 problem solves (A A^H + lambda I) u = lambda y, and x = A^H u / lambda.
+// Conjugate gradients with the diagonal k-space preconditioner as M^-1 = P;
+// every scalar stays on the device (no host synchronisation per iteration).
+
+// sum_i p_i |r_i|^2 (p per sample [M], per sample and coil [M][C], or 1)
+__global__ void k_red_pnorm(const float2* r, const float* p, int p_mc, int C, int64_t n, double* part) {
+    double acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 v = r[i];
+        const double w = p ? (double)(p_mc ? p[i] : p[i / C]) : 1.0;
+        acc += w * ((double)v.x * v.x + (double)v.y * v.y);
+    }
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+// init: r = lam y (r holds y), u = 0, d = P r
+__global__ void k_cg_init(float2* r, float2* u, float2* d, const float* p, int p_mc, int C, int64_t n, float lam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 v = make_float2(lam * r[i].x, lam * r[i].y);
+    const float w = p ? (p_mc ? p[i] : p[i / C]) : 1.f;
+    r[i] = v;
+    u[i] = make_float2(0.f, 0.f);
+    d[i] = make_float2(w * v.x, w * v.y);
+}
+
+// alpha = rz / dq; u += alpha d; r -= alpha q
+__global__ void k_cg_ur(float2* u, float2* r, const float2* d, const float2* q, const double* rz, const double* dq,
+                        int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float al = (float)(*rz / *dq);
+    const float2 dv = d[i], qv = q[i];
+    u[i] = make_float2(u[i].x + al * dv.x, u[i].y + al * dv.y);
+    r[i] = make_float2(r[i].x - al * qv.x, r[i].y - al * qv.y);
+}
+
+// beta = rz_new / rz; d = P r + beta d
+__global__ void k_cg_d(float2* d, const float2* r, const float* p, int p_mc, int C, int64_t n, const double* rz_new,
+                       const double* rz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float be = (float)(*rz_new / *rz);
+    const float w = p ? (p_mc ? p[i] : p[i / C]) : 1.f;
+    const float2 rv = r[i], dv = d[i];
+    d[i] = make_float2(w * rv.x + be * dv.x, w * rv.y + be * dv.y);
+}
+
+__global__ void k_axpy2(float2* q, const float2* d, float a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    q[i] = make_float2(q[i].x + a * d[i].x, q[i].y + a * d[i].y);
+}
+
+__global__ void k_scale_copy(const float2* a, float2* b, float f, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = make_float2(f * a[i].x, f * a[i].y);
+}
+
+static void pnorm(const float2* r, const float* p, int p_mc, int C, int64_t n, double* out, double* part,
+                  hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_red_pnorm, dim3(nb), dim3(256), 0, s, r, p, p_mc, C, n, part);
+    KP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, part, nb, out, 1.0, 0);
+    KP_LAUNCH_CHECK();
+}
+
+void l2_dual_cg_impl(Plan& P, const float2* y, const float* p, int p_kind, float lam, int iters, float2* x_out,
+                     float2* u_out, double* res_host, hipStream_t s) {
+    check_p(P, p, p_kind);
+    if (iters < 1 || iters > 8192) fail(KP_ERR_INVALID_ARG, "iters must lie in [1, 8192]");
+    if (!(lam > 0.f)) fail(KP_ERR_INVALID_ARG, "lambda must be > 0");
+    if (!P.kint4.p) fail(KP_ERR_UNSUPPORTED, "the dual solver needs a plan with coil maps or one coil");
+    const int C = (int)P.C;
+    const int64_t n = P.M * C;
+    const int p_mc = p_kind == KP_PRECOND_MC ? 1 : 0;
+    float2* r = P.kint2.as<float2>();
+    float2* d = P.kint.as<float2>();
+    float2* q = P.kint3.as<float2>();
+    float2* u = P.kint4.as<float2>();
+    float2* img = P.img[0].as<float2>();
+    double* sl = P.red.as<double>() + 2048;  // rz (two slots), dq, |r|^2, |r0|^2
+    double* part = P.red.as<double>() + 16;
+    permute_to_internal(y, r, P.perm.as<int32_t>(), P.M, C, s);
+    const float* pint = load_p(P, p, p_kind, s);
+    hipLaunchKernelGGL(k_cg_init, dim3(nblk(n)), dim3(256), 0, s, r, u, d, pint, p_mc, C, n, lam);
+    KP_LAUNCH_CHECK();
+    pnorm(r, pint, p_mc, C, n, sl + 0, part, s);
+    double r0 = 0;
+    if (res_host) {
+        reduce(r, nullptr, n, 0, sl + 4, 1.0, false, part, s);
+        KP_HIP(hipMemcpyAsync(&r0, sl + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+        KP_HIP(hipStreamSynchronize(s));
+        r0 = std::sqrt(r0);
+        res_host[0] = 1.0;
+    }
+    int cur = 0;
+    for (int it = 0; it < iters; ++it) {
+        // q = (A A^H + lam I) d
+        float2* g2 = spread_to_grid(P, d, C, s);
+        AdjOpts ao;
+        grid_to_image(P, g2, img, ao, s);
+        FwdOpts fo;
+        float2* grid = forward_to_grid(P, img, fo, s);
+        InterpArgs ia{};
+        ia.mode = IO_INTERNAL;
+        ia.out = q;
+        interp(P, grid, ia, s);
+        hipLaunchKernelGGL(k_axpy2, dim3(nblk(n)), dim3(256), 0, s, q, d, lam, n);
+        KP_LAUNCH_CHECK();
+        reduce(d, q, n, 3, sl + 2, 1.0, false, part, s);
+        hipLaunchKernelGGL(k_cg_ur, dim3(nblk(n)), dim3(256), 0, s, u, r, d, q, sl + cur, sl + 2, n);
+        KP_LAUNCH_CHECK();
+        pnorm(r, pint, p_mc, C, n, sl + (1 - cur), part, s);
+        hipLaunchKernelGGL(k_cg_d, dim3(nblk(n)), dim3(256), 0, s, d, r, pint, p_mc, C, n, sl + (1 - cur), sl + cur);
+        KP_LAUNCH_CHECK();
+        cur = 1 - cur;
+        if (res_host) {
+            double rr = 0;
+            reduce(r, nullptr, n, 0, sl + 3, 1.0, false, part, s);
+            KP_HIP(hipMemcpyAsync(&rr, sl + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+            KP_HIP(hipStreamSynchronize(s));
+            res_host[it + 1] = r0 > 0 ? std::sqrt(rr) / r0 : 0.0;
+        }
+    }
+    // x = A^H u / lam
+    float2* g2 = spread_to_grid(P, u, C, s);
+    AdjOpts ao;
+    grid_to_image(P, g2, img, ao, s);
+    hipLaunchKernelGGL(k_scale_copy, dim3(nblk(P.Ntot)), dim3(256), 0, s, img, x_out, 1.f / lam, P.Ntot);
+    KP_LAUNCH_CHECK();
+    if (u_out) permute_to_caller(u, u_out, P.perm.as<int32_t>(), P.M, C, s);
+}
+
 }  // namespace kp
 
 using namespace kp;
@@ -777,6 +916,15 @@ int pdhg_schedule_params(kp_plan_t plan, const float* p, int p_kind, const kp_pd
                            op.accel, params, params + K, params + 2 * K);
         hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, params + 3 * K, op.lambda);
         KP_LAUNCH_CHECK();
+    });
+}
+
+int l2_dual_cg(kp_plan_t plan, const void* y, const float* p, int p_kind, float lambda, int iters, void* x_out,
+               void* u_out, double* residual_host, void* stream) {
+    return guarded([&] {
+        if (!plan || !plan->impl || !y || !x_out) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        l2_dual_cg_impl(*plan->impl, (const float2*)y, p, p_kind, lambda, iters, (float2*)x_out, (float2*)u_out,
+                        residual_host, (hipStream_t)stream);
     });
 }
 

@@ -193,3 +193,53 @@ def test_pdhg_tv_parity(shape, C, M, pk, iters):
     np.testing.assert_allclose(hg, hist, rtol=1e-4)
     assert hg[-1] < hg[0]
     plan.close()
+
+
+DUAL_CASES = [
+    # shape, C, M, kind, precond, lam, iters
+    ((24, 32), 3, 1500, "random", "none", 0.05, 12),
+    ((24, 32), 3, 1500, "random", "sc", 0.05, 12),
+    ((24, 32), 3, 1500, "random", "mc", 0.05, 12),
+    ((32, 32), 1, 2048, "radial", "sc", 0.1, 10),
+    ((12, 16, 20), 2, 3200, "ute", "mc", 0.05, 8),
+    ((16, 16, 16), 8, 5000, "random", "sc", 0.05, 8),
+]
+
+
+@pytest.mark.parametrize("shape,C,M,kind,pk,lam,iters", DUAL_CASES)
+def test_l2_dual_cg_parity(shape, C, M, kind, pk, lam, iters):
+    kp = _kp()
+    print("dual cg case", shape, C, M, kind, pk, lam, iters, flush=True)
+    k, maps, x, y, op = problem(shape, C, M, 11, 1.25, 4, kind)
+    plan = plan_for(kp, k, shape, maps, 1.25, 4)
+    if pk == "none":
+        p = None
+    elif pk == "sc":
+        p = oprecond.efficient_nufft(None, k, shape, 1.25, 4)[0]
+    else:
+        p = oprecond.efficient_nufft(maps, k, shape, 1.25, 4)
+    ho = []
+    xo, uo = opdhg.l2_dual_pcg(op.forward, op.adjoint, y, p, shape, lam, iters, history=ho)
+    pt = None if p is None else dev(p, torch.float32)
+    xg, ug, hg = kp.l2_dual_cg(plan, dev(y, torch.complex64), pt, lam=lam, iters=iters, want_u=True,
+                               residuals=True)
+    assert rel(xg.cpu().numpy(), xo) < 1e-4
+    assert rel(ug.cpu().numpy(), uo) < 1e-4
+    np.testing.assert_allclose(hg, ho, rtol=1e-3, atol=1e-5)
+    assert hg[-1] < 0.5 * hg[0]
+    # x alone (no u, no history) is the same computation
+    x2 = kp.l2_dual_cg(plan, dev(y, torch.complex64), pt, lam=lam, iters=iters)
+    assert rel(x2.cpu().numpy(), xg.cpu().numpy()) < 1e-6
+    plan.close()
+
+
+def test_l2_dual_cg_invalid():
+    kp = _kp()
+    k, maps, x, y, op = problem((16, 16), 2, 500, 3)
+    plan = plan_for(kp, k, (16, 16), maps, 1.25, 4)
+    yt = dev(y, torch.complex64)
+    with pytest.raises(kp.KpError):
+        kp.l2_dual_cg(plan, yt, lam=0.0, iters=5)
+    with pytest.raises(kp.KpError):
+        kp.l2_dual_cg(plan, yt, lam=0.1, iters=0)
+    plan.close()

@@ -321,3 +321,26 @@ def test_tv_pdhg_reaches_optimality():
     xp, _, vp, _ = otv.tv_pdhg(f, a, y, p, shape, lam, 3000)
     assert max(otv.kkt_residuals(f, a, y, xp, vp, lam)) < 1e-6
     assert np.linalg.norm(xp - x) < 1e-6 * np.linalg.norm(x)
+
+
+def test_l2_dual_pcg_reaches_primal_solution():
+    """The dual route gives the primal CG minimiser of (A^H A + lam I) x = A^H y
+    (a different linear system), with and without the k-space preconditioner."""
+    shape = (12, 14)
+    rng = np.random.default_rng(51)
+    C = 3
+    k = synth.spiral_2d(6, 120, 2.0)
+    maps = synth.coil_maps(shape, C, rng)
+    f = lambda v: ndft.forward(v, maps, k, shape)
+    a = lambda u: ndft.adjoint(u, maps, k, shape)
+    y = f(synth.phantom(shape, rng)) + synth.noise((C, k.shape[0]), 1e-3, rng)
+    lam = 0.1
+    xc, _ = pdhg.cg_l2(f, a, y, shape, lam)
+    for p in (None, precond.efficient_exact(None, k, shape)[0], precond.efficient_exact(maps, k, shape)):
+        hist = []
+        x, u = pdhg.l2_dual_pcg(f, a, y, p, shape, lam, 300, history=hist)
+        assert np.linalg.norm(x - xc) < 1e-8 * np.linalg.norm(xc)
+        # the dual optimality condition itself
+        res = f(a(u)) + lam * u - lam * y
+        assert np.linalg.norm(res) < 1e-8 * np.linalg.norm(lam * y)
+        assert hist[0] == 1.0 and hist[-1] < 1e-8
