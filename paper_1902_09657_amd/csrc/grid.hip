@@ -386,6 +386,10 @@ constexpr int kTlStage = 12;   // halo loads per thread held in registers
 
 __host__ __device__ inline int tl_h2p(int H2) { return H2 + ((12 - H2 % 8) % 8); }
 
+// TB0..TB2: the tile shape as compile-time constants (0: taken from the
+// arguments).  With constants every halo index is a multiply-shift and the
+// 16 tap offsets fold into the LDS instructions' immediate offsets.
+template <int TB0, int TB1, int TB2>
 __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
     extern __shared__ float4 tl_smem[];
     const int ncg = a.C / 4;
@@ -414,7 +418,8 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             rem /= a.nb[ax];
         }
     }
-    const int H0 = a.B[0] + 3, H1 = a.B[1] + 3, H2 = a.B[2] + 3, H2P = tl_h2p(H2);
+    const int H0 = (TB0 ? TB0 : a.B[0]) + 3, H1 = (TB1 ? TB1 : a.B[1]) + 3, H2 = (TB2 ? TB2 : a.B[2]) + 3;
+    const int H2P = tl_h2p(H2);
     const int hcells = H0 * H1 * H2;
     float2* halo = reinterpret_cast<float2*>(tl_smem);                    // [H0][H1][H2P][4]
     float* tab = reinterpret_cast<float*>(halo + (size_t)H0 * H1 * H2P * 4);  // [kTlBatch][16]
@@ -493,15 +498,18 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             float2 hv[16];  // all 16 reads issued before the first use
 #pragma unroll
             for (int t = 0; t < 16; ++t) hv[t] = halo[hb + toff[t]];
+            // axis-1 taps first, then the axis-0 weight once per t0
             float ax = 0.f, ay = 0.f;
 #pragma unroll
             for (int t0 = 0; t0 < 4; ++t0) {
+                float sx = w1v[0] * hv[t0 * 4].x, sy = w1v[0] * hv[t0 * 4].y;
 #pragma unroll
-                for (int t1 = 0; t1 < 4; ++t1) {
-                    const float wt = w0v[t0] * w1v[t1];
-                    ax = fmaf(wt, hv[t0 * 4 + t1].x, ax);
-                    ay = fmaf(wt, hv[t0 * 4 + t1].y, ay);
+                for (int t1 = 1; t1 < 4; ++t1) {
+                    sx = fmaf(w1v[t1], hv[t0 * 4 + t1].x, sx);
+                    sy = fmaf(w1v[t1], hv[t0 * 4 + t1].y, sy);
                 }
+                ax = fmaf(w0v[t0], sx, ax);
+                ay = fmaf(w0v[t0], sy, ay);
             }
             ax += dpp_row_shr4(ax);
             ay += dpp_row_shr4(ay);
@@ -579,11 +587,16 @@ void launch_interp_tiles(int d, int W, const InterpArgs& a, const int4* items, i
         const int64_t nb = nitems * (a.C / 4);
         if (nb > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "interpolation grid too large");
         const size_t lds = interp_tl3_lds_bytes(a.B);
+        const bool b888 = a.B[0] == 8 && a.B[1] == 8 && a.B[2] == 8;
+        const void* fn = b888 ? (const void*)k_interp_tl3<8, 8, 8> : (const void*)k_interp_tl3<0, 0, 0>;
         if (lds > 65536) {
-            (void)hipFuncSetAttribute((const void*)k_interp_tl3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             (void)hipGetLastError();
         }
-        hipLaunchKernelGGL(k_interp_tl3, dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+        if (b888)
+            hipLaunchKernelGGL((k_interp_tl3<8, 8, 8>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+        else
+            hipLaunchKernelGGL((k_interp_tl3<0, 0, 0>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
         KP_LAUNCH_CHECK();
         return;
     }
