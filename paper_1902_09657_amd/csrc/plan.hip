@@ -331,6 +331,77 @@ __global__ void __launch_bounds__(kSpreadChunk) k_chunk_order(const float* gs, c
     }
 }
 
+// Spreading order of a whole work item (tile or piece of a split tile, at
+// most kItemOrderMax entries): the entries are dealt to the item's chunks by
+// their rank within their bucket (the first entry of every bucket, then the
+// second of every bucket, ...), so every chunk draws evenly from all buckets
+// and the owner threads of the spreading kernel get runs of similar length;
+// each chunk is then stably sorted by bucket.  Ranks follow the canonical
+// (ascending sample position) order, so the result is deterministic.
+constexpr int kItemOrderMax = 4096;
+
+__device__ int entry_bucket(const float* gs, int s, int tc0, int tc1, const Geom& gm) {
+    const int NB1 = gm.d == 3 ? gm.B[1] + gm.W - 1 : 1;
+    int bk = 0;
+    for (int ax = 0; ax < gm.d - 1; ++ax) {
+        const int cell = (int)floorf(gs[(int64_t)s * gm.d + ax]);
+        int l = cell - gm.W / 2 + 1 - (ax == 0 ? tc0 : tc1) * gm.B[ax];
+        if (l < -(gm.W - 1)) l += gm.G[ax];
+        else if (l > gm.B[ax] - 1) l -= gm.G[ax];
+        bk = ax == 0 ? l + gm.W - 1 : bk * NB1 + (l + gm.W - 1);
+    }
+    return bk;
+}
+
+__global__ void __launch_bounds__(256) k_item_order(const float* gs, const int32_t* touch, const int4* items,
+                                                    Geom gm, int32_t* stouch, uint16_t* scode) {
+    __shared__ int cnt[512];
+    __shared__ int bk_of[kItemOrderMax];   // canonical order
+    __shared__ int s_il[kItemOrderMax];    // interleaved order
+    __shared__ uint16_t b_il[kItemOrderMax];
+    const int4 it = items[blockIdx.x];
+    const int tile = it.x, start = it.y, n = it.z;
+    int tc[3] = {0, 0, 0}, rem = tile;
+    for (int ax = gm.d - 1; ax >= 0; --ax) {
+        tc[ax] = rem % gm.nb[ax];
+        rem /= gm.nb[ax];
+    }
+    const int nbk = gm.d == 3 ? (gm.B[0] + gm.W - 1) * (gm.B[1] + gm.W - 1) : gm.B[0] + gm.W - 1;
+    for (int b = threadIdx.x; b < 512; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int bk = entry_bucket(gs, touch[start + e], tc[0], tc[1], gm);
+        bk_of[e] = bk;
+        atomicAdd(&cnt[bk], 1);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int bk = bk_of[e];
+        int rank = 0;  // earlier entries of the same bucket
+        for (int q = 0; q < e; ++q) rank += bk_of[q] == bk;
+        // position in (rank, bucket) order
+        int ip = 0;
+        for (int b = 0; b < nbk; ++b) {
+            const int c = cnt[b];
+            ip += min(c, rank) + (b < bk && c > rank ? 1 : 0);
+        }
+        s_il[ip] = touch[start + e];
+        b_il[ip] = (uint16_t)bk;
+    }
+    __syncthreads();
+    for (int ip = threadIdx.x; ip < n; ip += blockDim.x) {
+        const int c0 = ip - ip % kSpreadChunk, c1 = min(n, c0 + kSpreadChunk);
+        const int bk = b_il[ip];
+        int pos = c0;
+        for (int q = c0; q < c1; ++q) {
+            const int bq = b_il[q];
+            pos += (bq < bk || (bq == bk && q < ip)) ? 1 : 0;
+        }
+        stouch[start + pos] = s_il[ip];
+        scode[start + pos] = (uint16_t)bk;
+    }
+}
+
 __global__ void k_maps_transpose(const float2* src, int64_t N, int C, float2* dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N * C) return;
@@ -640,12 +711,31 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     // ---- spreading order of the entries inside every chunk of every item
     {
         if (spread_nbk(d, kb_width, P->Bs) > 512) fail(KP_ERR_UNSUPPORTED, "too many tile buckets");
-        std::vector<int4> chunks;
-        for (const int4& it : items)
+        // items of at most kItemOrderMax entries are interleaved over their
+        // chunks; larger ones (only with a max_chunk above it) keep their
+        // chunks of consecutive entries
+        std::vector<int4> chunks, whole;
+        for (const int4& it : items) {
+            if (it.z <= 0) continue;
+            if (it.z <= kItemOrderMax) {
+                whole.push_back(it);
+                continue;
+            }
             for (int q = 0; q < it.z; q += kSpreadChunk)
                 chunks.push_back(make_int4(it.x, it.y + q, std::min(kSpreadChunk, it.z - q), 0));
+        }
         P->stouch.alloc(sizeof(int32_t) * std::max(ntouch, 1));
         P->scode.alloc(sizeof(uint16_t) * std::max(ntouch, 1));
+        if (!whole.empty()) {
+            DevBuf dit;
+            dit.alloc(sizeof(int4) * whole.size());
+            KP_HIP(hipMemcpy(dit.p, whole.data(), sizeof(int4) * whole.size(), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_item_order, dim3((unsigned)whole.size()), dim3(256), 0, s, P->g_sorted.as<float>(),
+                               P->touch.as<int32_t>(), dit.as<int4>(), gms, P->stouch.as<int32_t>(),
+                               P->scode.as<uint16_t>());
+            KP_LAUNCH_CHECK();
+            KP_HIP(hipStreamSynchronize(s));
+        }
         if (!chunks.empty()) {
             DevBuf dch;
             dch.alloc(sizeof(int4) * chunks.size());
