@@ -296,7 +296,16 @@ void copy2(const float2* a, float2* b, int64_t n, hipStream_t s);
 void reduce(const float2* a, const float2* b, int64_t n, int kind, double* out, double scale, bool accumulate,
             double* part, hipStream_t s);
 void reduce_min(const float* p, int64_t n, float* out, float* part, hipStream_t s);
-void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s);
+// prox steps fused into the wavelet passes: soft threshold *tau * lam on the
+// analysis, x/xbar update with theta on the last synthesis pass
+struct DwtFuse {
+    const float* tau;
+    float lam;
+    float2* ex;
+    float2* exbar;
+    const float* theta;
+};
+void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s, const DwtFuse* fz = nullptr);
 void power_method(Plan& P, const float* pint, int p_mc, int iters, float* lam_out, hipStream_t s);
 const float* load_p(Plan& P, const float* p, int p_kind, hipStream_t s);
 void upload_wavelet_constants();

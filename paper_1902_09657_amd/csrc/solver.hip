@@ -88,27 +88,6 @@ void copy2(const float2* a, float2* b, int64_t n, hipStream_t s) {
     KP_LAUNCH_CHECK();
 }
 
-// x_new = z (prox result), xbar = x_new + theta (x_new - x), x = x_new
-__global__ void k_extrapolate(const float2* xn, float2* x, float2* xbar, int64_t n, const float* theta) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float th = *theta;
-    const float2 a = xn[i], b = x[i];
-    xbar[i] = make_float2(a.x + th * (a.x - b.x), a.y + th * (a.y - b.y));
-    x[i] = a;
-}
-
-// complex soft threshold v max(1 - t/|v|, 0) with t = scale * (*tau)
-__global__ void k_soft(float2* v, int64_t n, const float* tau, float lam) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float t = *tau * lam;
-    const float2 a = v[i];
-    const float m = sqrtf(a.x * a.x + a.y * a.y);
-    const float f = m > t ? 1.f - t / m : 0.f;
-    v[i] = make_float2(a.x * f, a.y * f);
-}
-
 // ------------------------------------------------------------- reductions
 // Deterministic two-stage reductions: a fixed grid of partials, then one
 // block sums them in a fixed order.
@@ -246,6 +225,13 @@ struct DwtArgs {
     int inverse;
     int O, I;          // outer / inner counts of the [O][L][I] view
     int Ob, Ib;        // columns per block: Ob outers x Ib inners (at most 64)
+    // fused prox steps (0 / null: none)
+    int soft;          // analysis: 1 = threshold the details of this level, 2 = every coefficient
+    const float* tau;  // threshold = *tau * lam
+    float lam;
+    float2* ex;        // synthesis: write x_new to ex and ex + theta (x_new - ex_old) to exbar
+    float2* exbar;
+    const float* theta;
 };
 
 constexpr int kDwtK = 16;  // rows per thread at most
@@ -291,6 +277,16 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
         if (i < a.I) base = dwt_base(a, o, i);
     }
     const int sr = a.S[a.ax];
+    // the line lies in the approximation sub-block of the other axes (last
+    // axis only; decides which coefficients are details of this level)
+    bool olow = true;
+    if (LAST && a.soft == 1) {
+        int rem = blockIdx.x * NL + l;
+        for (int b = a.ax - 1; b >= 0; --b) {
+            olow = olow && (rem % a.n[b]) < a.n[b] / 2;
+            rem /= a.n[b];
+        }
+    }
     // LDS: line-major rows (padded) on the last axis, row-major otherwise
     const int LP = L + 1;
     auto lds = [&](int r) { return LAST ? l * LP + r : r * (NL + 1) + l; };
@@ -338,11 +334,25 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
                 acc.y += c_h[t] * va.y + c_g[t] * vd.y;
             }
         }
-        a.x[base + r * sr] = acc;
+        if (a.soft && (a.soft == 2 || r >= h2 || !olow)) {
+            const float t = *a.tau * a.lam;
+            const float m = sqrtf(acc.x * acc.x + acc.y * acc.y);
+            const float f = m > t ? 1.f - t / m : 0.f;
+            acc = make_float2(acc.x * f, acc.y * f);
+        }
+        if (a.ex) {
+            const int e = base + r * sr;
+            const float th = *a.theta;
+            const float2 xo = a.ex[e];
+            a.exbar[e] = make_float2(acc.x + th * (acc.x - xo.x), acc.y + th * (acc.y - xo.y));
+            a.ex[e] = acc;
+        } else {
+            a.x[base + r * sr] = acc;
+        }
     }
 }
 
-void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s) {
+void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream_t s, const DwtFuse* fz) {
     int64_t tot = 1;
     for (int b = 0; b < d; ++b) tot *= N[b];
     if (tot >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "wavelet: image too large");
@@ -361,6 +371,17 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
             a.d = d;
             a.ax = ax;
             a.inverse = inverse ? 1 : 0;
+            if (fz && !inverse && ax == d - 1) {
+                // the details of this level are final after its last axis
+                a.soft = lev == levels - 1 ? 2 : 1;
+                a.tau = fz->tau;
+                a.lam = fz->lam;
+            }
+            if (fz && inverse && lev == 0 && ax == 0) {
+                a.ex = fz->ex;
+                a.exbar = fz->exbar;
+                a.theta = fz->theta;
+            }
             a.O = 1;
             a.I = 1;
             for (int b = 0; b < ax; ++b) a.O *= n[b];
@@ -716,12 +737,12 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
             ao.epi = EPI_Z;
             ao.exbar = z;
             grid_to_image(P, g2, z, ao, s);
-            dwt(z, P.N, P.d, levels, false, s);
-            hipLaunchKernelGGL(k_soft, dim3(nblk(P.Ntot)), dim3(256), 0, s, z, P.Ntot, tau + k, op.lambda);
-            KP_LAUNCH_CHECK();
-            dwt(z, P.N, P.d, levels, true, s);
-            hipLaunchKernelGGL(k_extrapolate, dim3(nblk(P.Ntot)), dim3(256), 0, s, z, x, xbar, P.Ntot, th + k);
-            KP_LAUNCH_CHECK();
+            // x_new = W^H soft(W z): the soft threshold is fused into the
+            // analysis passes, x, xbar <- x_new, x_new + theta (x_new - x)
+            // into the last synthesis pass (levels >= 1 was checked)
+            DwtFuse fz{tau + k, op.lambda, x, xbar, th + k};
+            dwt(z, P.N, P.d, levels, false, s, &fz);
+            dwt(z, P.N, P.d, levels, true, s, &fz);
         }
         if (op.objective_host) op.objective_host[k + 1] = objective(P, x, yint, op.reg, op.lambda, levels, s);
     }

@@ -101,6 +101,9 @@ SOLVE_CASES = [
     # deepest wavelet levels with axes shorter than the filter (L = 2, 4, 6)
     ((16, 24), 2, 1500, 1.25, 4, "l1wav", 5e-3, "sc", 8, 3),
     ((8, 16, 12), 2, 2000, 1.25, 4, "l1wav", 5e-3, "none", 6, 2),
+    # one level: every coefficient is thresholded after the first level's last axis
+    ((24, 32), 3, 2000, 1.25, 4, "l1wav", 5e-3, "mc", 10, 1),
+    ((16, 16, 16), 2, 3000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 1),
 ]
 
 
