@@ -518,26 +518,53 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             if (t2 == 3) obuf[i * 4 + c] = make_float2(ax, ay);
         }
         __syncthreads();
-        // ---- output stage of the batch: all threads, consecutive (sample, coil)
-        for (int q = tid; q < nbt * 4; q += 256) {
-            const int64_t s = start + b0 + (q >> 2);
-            const int cc = cg * 4 + (q & 3);
-            const int64_t e = s * C + cc;
-            const float2 v = obuf[q];
+        // ---- output stage of the batch: one sample's 4 coils per thread
+        // (32 contiguous bytes of every [sample][coil] array, 16-byte accesses)
+        for (int i = tid; i < nbt; i += 256) {
+            const int64_t s = start + b0 + i;
+            const int64_t e = s * C + cg * 4;
+            const float4* ob = reinterpret_cast<const float4*>(obuf + i * 4);
+            const float4 v01 = ob[0], v23 = ob[1];
             if (a.mode == IO_CALLER) {
-                a.out[(int64_t)cc * a.M + a.perm[s]] = v;
-            } else if (a.mode == IO_INTERNAL) {
-                a.out[e] = v;
-            } else if (a.mode == IO_PMUL) {
-                const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-                a.out[e] = make_float2(pv * v.x, pv * v.y);
-            } else {  // IO_DUAL
-                const float pv = a.p ? (a.p_mc ? a.p[e] : a.p[s]) : 1.f;
-                const float sp = *a.sigma * pv;
-                const float den = 1.f / (1.f + sp);
-                const float2 u = a.u[e], y = a.y[e];
-                a.u[e] = make_float2((u.x + sp * (v.x - y.x)) * den, (u.y + sp * (v.y - y.y)) * den);
+                const int64_t ps = a.perm[s];
+                const int64_t c0 = (int64_t)(cg * 4) * a.M + ps;
+                a.out[c0] = make_float2(v01.x, v01.y);
+                a.out[c0 + a.M] = make_float2(v01.z, v01.w);
+                a.out[c0 + 2 * a.M] = make_float2(v23.x, v23.y);
+                a.out[c0 + 3 * a.M] = make_float2(v23.z, v23.w);
+                continue;
             }
+            float4* o4 = reinterpret_cast<float4*>(a.mode == IO_DUAL ? a.u + e : a.out + e);
+            if (a.mode == IO_INTERNAL) {
+                o4[0] = v01;
+                o4[1] = v23;
+                continue;
+            }
+            float4 pv = make_float4(1.f, 1.f, 1.f, 1.f);
+            if (a.p) {
+                if (a.p_mc) {
+                    pv = *reinterpret_cast<const float4*>(a.p + e);
+                } else {
+                    const float q = a.p[s];
+                    pv = make_float4(q, q, q, q);
+                }
+            }
+            if (a.mode == IO_PMUL) {
+                o4[0] = make_float4(pv.x * v01.x, pv.x * v01.y, pv.y * v01.z, pv.y * v01.w);
+                o4[1] = make_float4(pv.z * v23.x, pv.z * v23.y, pv.w * v23.z, pv.w * v23.w);
+                continue;
+            }
+            // IO_DUAL: u <- (u + sigma p (v - y)) / (1 + sigma p)
+            const float sg = *a.sigma;
+            const float4* y4 = reinterpret_cast<const float4*>(a.y + e);
+            const float4 u01 = o4[0], u23 = o4[1], y01 = y4[0], y23 = y4[1];
+            const float sp0 = sg * pv.x, sp1 = sg * pv.y, sp2 = sg * pv.z, sp3 = sg * pv.w;
+            const float d0 = 1.f / (1.f + sp0), d1 = 1.f / (1.f + sp1);
+            const float d2 = 1.f / (1.f + sp2), d3 = 1.f / (1.f + sp3);
+            o4[0] = make_float4((u01.x + sp0 * (v01.x - y01.x)) * d0, (u01.y + sp0 * (v01.y - y01.y)) * d0,
+                                (u01.z + sp1 * (v01.z - y01.z)) * d1, (u01.w + sp1 * (v01.w - y01.w)) * d1);
+            o4[1] = make_float4((u23.x + sp2 * (v23.x - y23.x)) * d2, (u23.y + sp2 * (v23.y - y23.y)) * d2,
+                                (u23.z + sp3 * (v23.z - y23.z)) * d3, (u23.w + sp3 * (v23.w - y23.w)) * d3);
         }
     }
 }
@@ -856,11 +883,22 @@ __global__ void k_reduce_partials(SpreadArgs a, const int4* heavy, int d) {
     }
     const int64_t i = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
     if (i < cells * C) {
-        // slots summed in order, four independent loads in flight
+        // slots summed in order; sixteen independent loads in flight (the
+        // dense centre of a radial trajectory splits one tile into 100+ slots)
         const float2* src = a.partial + (int64_t)h.y * cells * C + i;
         const int64_t st = cells * C;
         float2 s = make_float2(0.f, 0.f);
         int q = 0;
+        for (; q + 16 <= h.z; q += 16) {
+            float2 v[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) v[t] = src[(q + t) * st];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                s.x += v[t].x;
+                s.y += v[t].y;
+            }
+        }
         for (; q + 4 <= h.z; q += 4) {
             const float2 v0 = src[(q + 0) * st], v1 = src[(q + 1) * st];
             const float2 v2 = src[(q + 2) * st], v3 = src[(q + 3) * st];

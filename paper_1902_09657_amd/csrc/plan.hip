@@ -751,6 +751,8 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     P->nslots = nslots;
     P->work.alloc(sizeof(int4) * items.size());
     KP_HIP(hipMemcpy(P->work.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice));
+    // tiles with the most slots first: their reductions are the longest
+    std::stable_sort(heavy.begin(), heavy.end(), [](const int4& x, const int4& y) { return x.z > y.z; });
     P->heavy_list.alloc(sizeof(int4) * std::max<size_t>(heavy.size(), 1));
     if (!heavy.empty())
         KP_HIP(hipMemcpy(P->heavy_list.p, heavy.data(), sizeof(int4) * heavy.size(), hipMemcpyHostToDevice));

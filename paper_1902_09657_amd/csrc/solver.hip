@@ -259,7 +259,9 @@ __device__ __forceinline__ int dwt_base(const DwtArgs& a, int o, int i) {
 // Strided axes: lines are NL consecutive inner columns, lanes run across them
 // (coalesced over the columns).  Contiguous (last) axis: lanes run along a
 // line (coalesced over the rows).
-template <bool LAST, int NL>
+// FUSE: 0 plain; 1 soft threshold on the output (analysis, last axis);
+// 2 write x / xbar instead of the output (synthesis).
+template <bool LAST, int NL, int FUSE = 0>
 __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
     extern __shared__ float2 buf[];
     constexpr int P = 256 / NL;
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
     // the line lies in the approximation sub-block of the other axes (last
     // axis only; decides which coefficients are details of this level)
     bool olow = true;
-    if (LAST && a.soft == 1) {
+    if (LAST && FUSE == 1 && a.soft == 1) {
         int rem = blockIdx.x * NL + l;
         for (int b = a.ax - 1; b >= 0; --b) {
             olow = olow && (rem % a.n[b]) < a.n[b] / 2;
@@ -334,13 +336,13 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
                 acc.y += c_h[t] * va.y + c_g[t] * vd.y;
             }
         }
-        if (a.soft && (a.soft == 2 || r >= h2 || !olow)) {
+        if (FUSE == 1 && (a.soft == 2 || r >= h2 || !olow)) {
             const float t = *a.tau * a.lam;
             const float m = sqrtf(acc.x * acc.x + acc.y * acc.y);
             const float f = m > t ? 1.f - t / m : 0.f;
             acc = make_float2(acc.x * f, acc.y * f);
         }
-        if (a.ex) {
+        if (FUSE == 2) {
             const int e = base + r * sr;
             const float th = *a.theta;
             const float2 xo = a.ex[e];
@@ -401,8 +403,13 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
             else
                 nb = (int64_t)a.O * ((a.I + NL - 1) / NL);
             void (*fn)(DwtArgs);
-            if (ax == d - 1)
+            if (ax == d - 1 && a.soft)
+                fn = NL == 8 ? k_dwt_pass<true, 8, 1> : (NL == 4 ? k_dwt_pass<true, 4, 1> : k_dwt_pass<true, 1, 1>);
+            else if (ax == d - 1)
                 fn = NL == 8 ? k_dwt_pass<true, 8> : (NL == 4 ? k_dwt_pass<true, 4> : k_dwt_pass<true, 1>);
+            else if (a.ex)
+                fn = NL == 16 ? k_dwt_pass<false, 16, 2>
+                              : (NL == 4 ? k_dwt_pass<false, 4, 2> : k_dwt_pass<false, 1, 2>);
             else
                 fn = NL == 16 ? k_dwt_pass<false, 16> : (NL == 4 ? k_dwt_pass<false, 4> : k_dwt_pass<false, 1>);
             if (lds > 65536) {
