@@ -68,7 +68,7 @@ def byte_model(shape, G, C, M, d):
             "total": fwd_fft + interp + spread + adj_fft, "grid": grid}
 
 
-KERNEL_NAMES = {"interp": "k_interp_tl3", "spread": "k_spread<3,4,4,4>"}
+KERNEL_NAMES = {"interp": "k_interp_tl3<8,8,8>", "spread": "k_spread<3,4,4,4,true>"}
 # sources whose change invalidates a committed counter measurement
 TRAFFIC_SOURCES = ["paper_1902_09657_amd/csrc/grid.hip", "paper_1902_09657_amd/csrc/plan.hip",
                    "paper_1902_09657_amd/csrc/kp_internal.h"]
