@@ -743,8 +743,11 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
                 }
             }
         }
-        // low 16 bits: bucket; high bits: its axis-1 coordinate (3D)
-        code[e] = bk | ((D == 3 ? bk % NB1 : 0) << 16);
+        // low 16 bits: bucket; high 16 bits (signed): the byte offset
+        // 4 (e - b1 EP) with b1 the bucket's axis-1 coordinate, so that the
+        // axis-1 weight of this entry for line j1 sits (2W - 1 + j1) EP floats
+        // past wl plus that offset (3D)
+        code[e] = bk | (int)((unsigned)(4 * (e - (D == 3 ? bk % NB1 : 0) * EP)) << 16);
         if (uv) {
 #pragma unroll
             for (int c = 0; c < 8; ++c)
@@ -814,12 +817,13 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
         }
         // ---- C: each owner thread gathers the entries covering its line
         if (owner) {
+            const char* wly = reinterpret_cast<const char*>(wl + (2 * W - 1 + j1) * EP);
             // the W buckets of one q0 along axis 1 are consecutive, so their
             // entries form one contiguous run; the axis-1 tap of an entry
             // follows from its bucket coordinate b1
             auto gather = [&](int idx, int t0) {
                 float wA = wl[t0 * EP + idx];
-                if (D == 3) wA *= wl[(W + j1 + W - 1 - (code[idx] >> 16)) * EP + idx];
+                if (D == 3) wA *= *reinterpret_cast<const float*>(wly + (code[idx] >> 16));
                 const float2* up = uu + (cg * CG) * EP + idx;
                 float2 uv[CG];
 #pragma unroll
