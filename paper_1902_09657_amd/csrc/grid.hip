@@ -20,8 +20,9 @@
 // along the last axis (and a group of coils) in registers.  A thread visits
 // exactly the samples that cover its line, so there are no atomics at all
 // for an owned tile; a tile whose touch list was split over several work
-// items (the dense k-space centre) adds its registers into a pre-zeroed grid
-// region with global float atomics.
+// items (the dense k-space centre) writes each piece's registers to a slot of
+// partial tiles, and the slots of a tile are added in slot order afterwards,
+// so results are bit-reproducible.
 #include <algorithm>
 #include <cmath>
 
