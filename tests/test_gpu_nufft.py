@@ -103,7 +103,8 @@ def test_forward_adjoint_parity(shape, C, M, alpha, W):
 
 
 def test_heavy_tiles_split_path():
-    """Tiny chunks force every busy tile through the split (atomic) path."""
+    """Tiny chunks force every busy tile through the split path (partial
+    tiles added in slot order)."""
     kp = _kp()
     shape, C = (24, 28), 3
     k, maps, x, y = case(shape, C, 2500, 13, 1.25, 4)
@@ -117,6 +118,26 @@ def test_heavy_tiles_split_path():
         yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
         assert rel(yg, op.forward(x)) < 1e-4
         plan.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 8192])
+def test_work_items_beyond_interleave_limit(chunk):
+    """5000 samples at k = 0: with max_chunk 8192 the centre tiles form work
+    items of more than 4096 entries, which keep their chunks of consecutive
+    entries; the default splits them into interleaved items."""
+    kp = _kp()
+    shape, C = (32, 32), 4
+    k, maps, x, y = case(shape, C, 9000, 17, 1.25, 4)
+    k[:5000] = 0.0
+    op = onufft.Nufft(k, shape, maps, 1.25, 4)
+    plan = _plan(kp, k, shape, maps, 1.25, 4, max_chunk=chunk)
+    if chunk:
+        assert plan.info()["heavy_tiles"] == 0
+    xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
+    assert rel(xg, op.adjoint(y)) < 1e-4
+    yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
+    assert rel(yg, op.forward(x)) < 1e-4
+    plan.close()
 
 
 @pytest.mark.parametrize("C,bins", [(8, None), (4, (5, 10, 5)), (12, (8, 10, 6)), (4, (8, 10, 3))])
