@@ -271,8 +271,8 @@ static int lds_limit() {
 
 // ------------------------------------------------------------------------
 // Specialised pass for the transform lengths of the benchmark workloads: the
-// length, the radix sequence and the column block (NC = 8 or 16 columns, a
-// divisor of the 256 threads, so every thread keeps one column) are compile
+// length, the radix sequence and the column block (NC = 8, 16 or 32 columns,
+// a divisor of the 256 threads, so every thread keeps one column) are compile
 // time constants, every index is a shift or a multiply, and the stages run
 // in place in a single LDS buffer with the butterfly inputs held in
 // registers across the barrier.
@@ -515,7 +515,7 @@ static bool batch_length(int L) { return L == 160 || L == 200 || L == 240 || L =
 bool fft_batchable(const FftPass& p) {
     const int nc = p.Ob * p.Ib;
     const int nt = fixed_threads(nc);
-    if (nc != 32 && nc != 16 && nc != 12) return false;
+    if (nc != 32 && nc != 16 && nc != 12 && nc != 8) return false;
     if (p.post == POST_MAPS && (nt % p.Ob) != 0) return false;
     return batch_length(p.L);
 }
@@ -530,6 +530,7 @@ void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n
     const size_t lds = sizeof(float2) * (size_t)maxL * (nc + 1);
     const void* fn = nc == 12   ? (const void*)k_fft_batch<12, 192>
                      : nc == 32 ? (const void*)k_fft_batch<32, 256>
+                     : nc == 8  ? (const void*)k_fft_batch<8, 256>
                                 : (const void*)k_fft_batch<16, 256>;
     if (lds > 65536) {
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -539,6 +540,8 @@ void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n
         hipLaunchKernelGGL((k_fft_batch<12, 192>), dim3((unsigned)nblk), dim3(192), lds, s, d_passes, d_blk_start, n);
     else if (nc == 32)
         hipLaunchKernelGGL((k_fft_batch<32, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
+    else if (nc == 8)
+        hipLaunchKernelGGL((k_fft_batch<8, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
     else
         hipLaunchKernelGGL((k_fft_batch<16, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
     KP_LAUNCH_CHECK();

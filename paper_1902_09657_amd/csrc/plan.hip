@@ -854,7 +854,7 @@ void pass_blocking(int64_t I, int* Ob, int* Ib) {
         *Ob = 1;
     } else {
         *Ib = (int)I;
-        *Ob = std::max<int>(1, 16 / (int)I);
+        *Ob = std::max<int>(1, 8 / (int)I);  // short inner axis (the coils): 8 columns
     }
 }
 
@@ -956,7 +956,7 @@ std::vector<FftPass> adjoint_passes(Plan& P, float2* grid, float2* out, const Ad
             fp.e_lam = o.lam;
             if (!o.channel) {
                 fp.Ib = C;
-                fp.Ob = std::max(1, 16 / C);
+                fp.Ob = std::max(1, 8 / C);
             } else {
                 pass_blocking(I, &fp.Ob, &fp.Ib);
             }
