@@ -58,7 +58,9 @@ enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1, KP_REG_TV = 2 };
 typedef struct {
     int bin_size[3];        /* sort / interpolation tile edge per axis; divides G_a */
     int max_chunk;          /* max touch-list entries per spreading work item        */
-    int spread_bin_size[3]; /* spreading tile edge per axis; divides G_a             */
+    int spread_bin_size[3]; /* spreading tile edge per axis; divides G_a; last axis
+                               <= 8; in 3D axis 1 + W <= 65 (else
+                               KP_ERR_UNSUPPORTED)                                   */
 } kp_tuning;
 
 /* Shape facts of a plan (filled by nufft_plan_info, host struct). */

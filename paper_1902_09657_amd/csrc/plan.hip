@@ -596,6 +596,10 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     P->nbins = (int64_t)P->nb[0] * P->nb[1] * P->nb[2];
     P->nstiles = (int64_t)P->nbs[0] * P->nbs[1] * P->nbs[2];
     if (spread_threads(ndim, P->Bs, C) > 256) fail(KP_ERR_INVALID_ARG, "spreading tiles need more than 256 threads");
+    // the spreading kernel keeps a signed 16-bit LDS byte offset per entry for
+    // its axis-1 weight: 4 (B_1 + W - 2)(chunk + 1) must stay below 2^15
+    if (ndim == 3 && 4 * (P->Bs[1] + kb_width - 2) * (kSpreadChunk + 1) > 32767)
+        fail(KP_ERR_UNSUPPORTED, "spreading tiles longer than 64 - W cells on axis 1 are not supported");
     P->spread_lds = (int)spread_lds_bytes(ndim, kb_width, P->Bs, C);
     if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading chunk does not fit in LDS");
     if (P->nbins >= ((int64_t)1 << 31) || P->nstiles >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");

@@ -208,6 +208,11 @@ def test_edge_cases():
         with pytest.raises(kp.KpError) as ei:
             _plan(kp, bad, shape, None, 2.0, 4)
         assert ei.value.code == -1
+    # 3D spreading tiles too long on axis 1 for the per-entry weight offset
+    k3 = np.zeros((4, 3), np.float32)
+    with pytest.raises(kp.KpError) as ei:
+        _plan(kp, k3, (16, 64, 16), None, 2.0, 2, spread_bin_size=(1, 64, 4))
+    assert ei.value.code == -2
     # coordinates slightly beyond pi wrap periodically
     k2 = np.array([[math.pi + 0.3, -math.pi - 0.2], [0.1, 0.2]], np.float32)
     plan = _plan(kp, k2, shape, None, 2.0, 4)
