@@ -287,7 +287,10 @@ def bench_context(kp, dev):
     """Context runs (not the headline): (1) P = I vs SC vs MC on the 2D spiral
     workload (256^2, 8 coils, l1-db4, 30 iterations): normalised objective gap
     (f_k - f*) / (f_0 - f*) with f* from 300 MC-preconditioned iterations, and
-    the time per iteration; (2) preconditioner build time at the two fully
+    the time per iteration; (2) the l2 problem (lambda 1e-2) solved through
+    its dual by CG preconditioned with P = I, SC, MC against the SC / MC
+    preconditioned PDHG, as the distance to x* per iteration; (3)
+    preconditioner build time at the two fully
     specified shapes of the paper's Table I (synthetic trajectories and maps;
     the 255 x 200 brain matrix is taken as 256 x 200 since image extents must be
     even here), beside the paper's Titan Xp figures."""
@@ -319,9 +322,40 @@ def bench_context(kp, dev):
         gap = [(h - fstar) / (hist[0] - fstar) for h in hist]
         comp[name] = {"gap_at": {str(i): float("%.4g" % gap[i]) for i in (5, 10, 20, 30)},
                       "ms_per_iter_incl_power_method": round(e0.elapsed_time(e1) / 30, 4)}
-    plan.close()
     out["precond_comparison"] = {"workload": cfg.name + ", l1-db4 lambda 5e-3, 30 iterations",
                                  "reference": "f* = min objective of 300 MC iterations", "gap": comp}
+    # (3) l2 (lambda 1e-2, the paper's l2 value): the dual solve by k-space
+    # preconditioned CG vs the preconditioned PDHG, relative distance to x*
+    lam2 = 1e-2
+    xs = kp.pdhg_solve(plan, y, ps["mc"], reg="l2", lam=lam2, iters=500)
+    nrm = float(torch.linalg.vector_norm(xs))
+    l2 = {}
+    for name in ("none", "sc", "mc"):
+        row = {}
+        for it in (5, 10, 20, 30):
+            xk = kp.l2_dual_cg(plan, y, ps[name], lam=lam2, iters=it)
+            row[str(it)] = float("%.4g" % (float(torch.linalg.vector_norm(xk - xs)) / nrm))
+        torch.cuda.synchronize()
+        e0.record(s)
+        kp.l2_dual_cg(plan, y, ps[name], lam=lam2, iters=30)
+        e1.record(s)
+        torch.cuda.synchronize()
+        l2["dual_pcg_" + name] = {"rel_err_at": row, "ms_per_iter": round(e0.elapsed_time(e1) / 30, 4)}
+    for name in ("sc", "mc"):
+        row = {}
+        for it in (5, 10, 20, 30):
+            xk = kp.pdhg_solve(plan, y, ps[name], reg="l2", lam=lam2, iters=it)
+            row[str(it)] = float("%.4g" % (float(torch.linalg.vector_norm(xk - xs)) / nrm))
+        torch.cuda.synchronize()
+        e0.record(s)
+        kp.pdhg_solve(plan, y, ps[name], reg="l2", lam=lam2, iters=30)
+        e1.record(s)
+        torch.cuda.synchronize()
+        l2["pdhg_" + name] = {"rel_err_at": row, "ms_per_iter_incl_power_method": round(e0.elapsed_time(e1) / 30, 4)}
+    plan.close()
+    out["l2_dual_cg_vs_pdhg"] = {"workload": cfg.name + ", l2 lambda 1e-2",
+                                 "reference": "x* = 500 MC-preconditioned PDHG iterations",
+                                 "rel_err = |x_k - x*| / |x*|": l2}
     # Table I shapes
     rows = []
     rng = np.random.default_rng(7)
