@@ -2,7 +2,8 @@
 
 * 2D radial 128^2 (1 coil, SC, l2, 20 iterations) and 2D spiral 256^2 (8 coils,
   MC, l1-db4, 30 iterations): the whole solve against the oracle; the spiral
-  workload also with the TV regulariser.
+  workload also with the TV regulariser and, for l2, through its dual (10
+  MC-preconditioned CG iterations).
 * 3D UTE 160^3, 8 coils, 2.56 M samples/coil (the timed workload, same plan as
   the benchmark): the full forward and adjoint against the oracle, the adjoint
   identity, and the first two PDHG iterations against the oracle (P = I and a
@@ -88,6 +89,27 @@ def test_2d_spiral_workload_tv_solve():
                            iters=cfg.iters, objective=True)
     assert rel(xg.cpu().numpy(), xo) < 1e-4
     np.testing.assert_allclose(hg, hist, rtol=1e-4)
+    plan.close()
+
+
+def test_2d_spiral_workload_l2_dual_cg():
+    """The 2D spiral workload's data (256^2, 8 coils) solved for l2 through its
+    dual: MC-preconditioned CG, 10 iterations, x, u and the residual history."""
+    kp = _kp()
+    cfg = synth.config(2)
+    x, maps, k, w = cfg.inputs(seed=2)
+    op = onufft.Nufft(k, cfg.shape, maps, cfg.alpha, cfg.width)
+    y = op.forward(x) + w
+    p = oprecond.efficient_nufft(maps, k, cfg.shape, cfg.alpha, cfg.width)
+    ho = []
+    xo, uo = opdhg.l2_dual_pcg(op.forward, op.adjoint, y, p, cfg.shape, 1e-2, 10, history=ho)
+    plan = _plan(kp, k, cfg.shape, maps, cfg.alpha, cfg.width)
+    xg, ug, hg = kp.l2_dual_cg(plan, dev(y, torch.complex64), dev(p, torch.float32), lam=1e-2, iters=10,
+                               want_u=True, residuals=True)
+    print("dual cg x rel", rel(xg.cpu().numpy(), xo), flush=True)
+    assert rel(xg.cpu().numpy(), xo) < 1e-4
+    assert rel(ug.cpu().numpy(), uo) < 1e-4
+    np.testing.assert_allclose(hg, ho, rtol=1e-3, atol=1e-5)
     plan.close()
 
 
