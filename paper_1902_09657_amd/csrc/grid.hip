@@ -429,19 +429,40 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
     const int tid = threadIdx.x;
 
     // ---- halo loads into registers (two coils per float4)
+    // 8^3 tiles (11^3 halo): thread t < 242 takes float4 t % 22 of the z-rows
+    // (h0, h1 = t / 22) for h0 = 0..10, so only h0 varies between its loads;
+    // other shapes: the halo's float4s dealt out in order.
+    constexpr bool ROWS = TB0 == 8 && TB1 == 8 && TB2 == 8;
     float4 hv[kTlStage];
-#pragma unroll
-    for (int r = 0; r < kTlStage; ++r) {
-        const int i = tid + r * 256;
-        if (i < hcells * 2) {
-            const int cell = i >> 1, part = i & 1;
-            const int h2 = cell % H2, h01 = cell / H2, h1 = h01 % H1, h0 = h01 / H1;
-            int j0 = org[0] - 1 + h0, j1 = org[1] - 1 + h1, j2 = org[2] - 1 + h2;
-            j0 = j0 < 0 ? j0 + a.G[0] : (j0 >= a.G[0] ? j0 - a.G[0] : j0);
+    if (ROWS) {
+        if (tid < 242) {
+            const int h1 = tid / 22, pos = tid % 22, h2 = pos >> 1, part = pos & 1;
+            int j1 = org[1] - 1 + h1, j2 = org[2] - 1 + h2;
             j1 = j1 < 0 ? j1 + a.G[1] : (j1 >= a.G[1] ? j1 - a.G[1] : j1);
             j2 = j2 < 0 ? j2 + a.G[2] : (j2 >= a.G[2] ? j2 - a.G[2] : j2);
-            const int64_t gi = ((int64_t)j0 * a.G[1] + j1) * a.G[2] + j2;
-            hv[r] = *reinterpret_cast<const float4*>(a.grid + gi * C + cg * 4 + part * 2);
+            const float2* rowp = a.grid + ((int64_t)j1 * a.G[2] + j2) * C + cg * 4 + part * 2;
+            const int64_t plane = (int64_t)a.G[1] * a.G[2] * C;
+#pragma unroll
+            for (int r = 0; r < 11; ++r) {
+                int j0 = org[0] - 1 + r;
+                j0 = j0 < 0 ? j0 + a.G[0] : (j0 >= a.G[0] ? j0 - a.G[0] : j0);
+                hv[r] = *reinterpret_cast<const float4*>(rowp + j0 * plane);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kTlStage; ++r) {
+            const int i = tid + r * 256;
+            if (i < hcells * 2) {
+                const int cell = i >> 1, part = i & 1;
+                const int h2 = cell % H2, h01 = cell / H2, h1 = h01 % H1, h0 = h01 / H1;
+                int j0 = org[0] - 1 + h0, j1 = org[1] - 1 + h1, j2 = org[2] - 1 + h2;
+                j0 = j0 < 0 ? j0 + a.G[0] : (j0 >= a.G[0] ? j0 - a.G[0] : j0);
+                j1 = j1 < 0 ? j1 + a.G[1] : (j1 >= a.G[1] ? j1 - a.G[1] : j1);
+                j2 = j2 < 0 ? j2 + a.G[2] : (j2 >= a.G[2] ? j2 - a.G[2] : j2);
+                const int64_t gi = ((int64_t)j0 * a.G[1] + j1) * a.G[2] + j2;
+                hv[r] = *reinterpret_cast<const float4*>(a.grid + gi * C + cg * 4 + part * 2);
+            }
         }
     }
 
@@ -472,7 +493,18 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             row[2] = make_float4(w[2][0], w[2][1], w[2][2], w[2][3]);
             row[3] = make_float4(__int_as_float((l[0] * H1 + l[1]) * H2P + l[2]), 0.f, 0.f, 0.f);
         }
-        if (b0 == 0) {
+        if (b0 == 0 && ROWS) {
+            if (tid < 242) {
+                const int h1 = tid / 22, pos = tid % 22;
+                float2* dst = halo + ((size_t)h1 * H2P + (pos >> 1)) * 4 + (pos & 1) * 2;
+#pragma unroll
+                for (int r = 0; r < 11; ++r) {
+                    float2* d = dst + (size_t)r * H1 * H2P * 4;
+                    d[0] = make_float2(hv[r].x, hv[r].y);
+                    d[1] = make_float2(hv[r].z, hv[r].w);
+                }
+            }
+        } else if (b0 == 0) {
 #pragma unroll
             for (int r = 0; r < kTlStage; ++r) {
                 const int i = tid + r * 256;
