@@ -355,6 +355,16 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
     const int64_t o = o0 + col / p.Ib, i = i0 + col % p.Ib;
     const bool live = o < p.O && i < p.I;
     const float xs = p.xscale ? *p.xscale : 1.f;
+    // support pruning (passes along axis 0 in 3D): rows [xlo, xhi) of this
+    // thread's column, from the range of its spreading tile column
+    int xlo = 0, xhi = L;
+    if (p.xr_mode && live) {
+        const int64_t yy = i / p.xr_G2C;
+        const int zz = (int)((i % p.xr_G2C) / p.xr_C);
+        const int2 r = p.xr[(yy / p.xr_B1) * p.xr_nb2 + zz / p.xr_B2];
+        xlo = r.x;
+        xhi = r.y;
+    }
 
     // ---- load (pruned): every row load of this thread is issued before the
     // first LDS write, so the block has all its loads in flight at once
@@ -363,7 +373,15 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
     constexpr int NR = (L + RS - 1) / RS;
     float2 v[NR];
     const int64_t oc = live ? o : 0, ic = live ? i : 0;
-    if (p.pre == PRE_NONE) {
+    if (p.pre == PRE_NONE && p.xr_mode == 2) {
+        // rows outside the support range are zero (spreading leaves them empty)
+        const float2* src = p.in + oc * p.in_os + ic;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int r = min(rb + k * RS, p.Lin - 1);
+            v[k] = (r >= xlo && r < xhi) ? src[(int64_t)r * p.in_rs] : make_float2(0.f, 0.f);
+        }
+    } else if (p.pre == PRE_NONE) {
         const float2* src = p.in + oc * p.in_os + ic;
 #pragma unroll
         for (int k = 0; k < NR; ++k) v[k] = src[(int64_t)min(rb + k * RS, p.Lin - 1) * p.in_rs];
@@ -458,6 +476,7 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
     }
     if (!live) return;
     for (int m = rb; m < p.Lout; m += RS) {
+        if (p.xr_mode == 1 && (m < xlo || m >= xhi)) continue;  // nothing reads these rows
         int q = m;
         if (p.crop_out) {
             q = m - p.Lout / 2;
@@ -589,10 +608,20 @@ static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     return true;
 }
 
+bool fft_fixed_ok(int L, int nc) {
+    const int nt = fixed_threads(nc);
+    if (nt == 0) return false;
+    fft_kernel_t fn = nc == 32 ? fixed_for<32, 256>(L) : nc == 16 ? fixed_for<16, 256>(L)
+                    : nc == 8 ? fixed_for<8, 256>(L) : fixed_for<12, 192>(L);
+    return fn && sizeof(float2) * (size_t)L * (nc + 1) <= (size_t)lds_limit();
+}
+
 void launch_fft_pass(const FftPass& pin, hipStream_t s) {
     FftPass p = pin;
     const int lim = lds_limit();
     if (launch_fixed(p, s, lim)) return;
+    // support-pruned loads exist only in the specialised kernel
+    if (p.xr_mode == 2) fail(KP_ERR_UNSUPPORTED, "support-pruned FFT pass needs the specialised kernel");
     // shrink the column block until both LDS buffers fit
     while (fft_lds_bytes(p.L, p.Ob * p.Ib) > (size_t)lim) {
         if (p.Ob > 1)

@@ -100,9 +100,19 @@ struct FftPass {
     const float* e_theta;
     float e_lambda;
     const float* e_lam;            // device lambda (overrides e_lambda when set)
+    // support pruning of the passes along axis 0 in 3D: xr[ty nb2 + tz] is the
+    // axis-0 cell range [lo, hi) holding every non-empty spreading tile of
+    // tile column (ty, tz); rows outside it are not stored (xr_mode 1, the last
+    // forward pass: nothing reads them) or not loaded and taken as zero
+    // (xr_mode 2, the first adjoint pass: spreading leaves them zero)
+    const int2* xr;
+    int xr_mode;
+    int xr_G2C, xr_C, xr_B1, xr_B2, xr_nb2;
 };
 
 void launch_fft_pass(const FftPass& p, hipStream_t s);
+// the specialised pass kernel handles length L with nc columns per block
+bool fft_fixed_ok(int L, int nc);
 void fft_factor(int L, int* nst, int* rad);
 size_t fft_lds_bytes(int L, int ncol);
 
@@ -202,6 +212,7 @@ struct Plan {
     DevBuf coords;                // caller's coordinates [M][d]
     DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
     DevBuf stouch, scode;         // touch entries in spreading order, their buckets
+    DevBuf xrange;                // 3D: axis-0 cell range of the non-empty spreading tiles per (ty, tz)
     DevBuf partial;               // partial tiles of split tiles
     DevBuf iwork;                 // interpolation pieces (tile, start, count, 0)
     int64_t niwork = 0;

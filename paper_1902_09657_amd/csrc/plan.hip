@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <algorithm>
+#include <climits>
 
 #include "kp_internal.h"
 
@@ -676,11 +677,45 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     // owned tiles by decreasing entry count): the density of a radial
     // trajectory is concentrated in a few tiles, and this order keeps every
     // compute unit busy to the end.
+    // 3D support pruning: per spreading tile column (ty, tz) the axis-0 cell
+    // range holding its non-empty tiles.  Empty tiles outside these ranges are
+    // then never written: the last forward FFT pass stores only the ranges
+    // (interpolation reads nothing else) and the first adjoint pass takes the
+    // rows outside them as zero.
+    // It needs the specialised FFT kernel for the axis-0 passes (32 columns).
+    // (G_1 G_2 >= 32: an axis-0 pass always has 32 columns per block)
+    const bool prune = d == 3 && (int64_t)P->G[1] * P->G[2] >= 32 && fft_fixed_ok(P->G[0], 32);
+    std::vector<char> skip;  // empty tiles outside their column's range
+    if (prune) {
+        const int nb1 = P->nbs[1], nb2 = P->nbs[2];
+        std::vector<int2> xr((size_t)nb1 * nb2, make_int2(INT_MAX, 0));
+        for (int64_t t = 0; t < P->nstiles; ++t) {
+            if (toff[t + 1] == toff[t]) continue;
+            const int tz = (int)(t % nb2), ty = (int)((t / nb2) % nb1), tx = (int)(t / ((int64_t)nb1 * nb2));
+            int2& r = xr[(size_t)ty * nb2 + tz];
+            r.x = std::min(r.x, tx * P->Bs[0]);
+            r.y = std::max(r.y, (tx + 1) * P->Bs[0]);
+        }
+        for (int2& r : xr)
+            if (r.y <= r.x) r = make_int2(0, 0);
+        P->xrange.alloc(sizeof(int2) * xr.size());
+        KP_HIP(hipMemcpy(P->xrange.p, xr.data(), sizeof(int2) * xr.size(), hipMemcpyHostToDevice));
+        // an empty tile inside its column's range is still written (zeros):
+        // the first adjoint pass reads the whole range
+        skip.assign((size_t)P->nstiles, 0);
+        for (int64_t t = 0; t < P->nstiles; ++t) {
+            if (toff[t + 1] != toff[t]) continue;
+            const int tz = (int)(t % nb2), ty = (int)((t / nb2) % nb1), tx = (int)(t / ((int64_t)nb1 * nb2));
+            const int2 r = xr[(size_t)ty * nb2 + tz];
+            skip[t] = (tx * P->Bs[0] >= r.y || (tx + 1) * P->Bs[0] <= r.x) ? 1 : 0;
+        }
+    }
     std::vector<int4> heavy_items, light_items;
     std::vector<int4> heavy;  // (tile, first slot, slots, 0)
     int nslots = 0;
     for (int64_t t = 0; t < P->nstiles; ++t) {
         const int o = toff[t], n = toff[t + 1] - toff[t];
+        if (prune && skip[t]) continue;  // an empty tile outside the range: never read
         if (n <= max_chunk) {
             light_items.push_back(make_int4((int)t, o, n, -1));
         } else {
@@ -828,7 +863,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_HIP(hipStreamSynchronize(s));
 
     int64_t total = 0;
-    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->touch_off, &P->touch, &P->work,
+    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->xrange, &P->touch_off, &P->touch, &P->work,
                       &P->heavy_list, &P->maps, &P->fo_fwd, &P->fr_fwd, &P->bufA, &P->bufB, &P->kint, &P->kint2, &P->kint3,
                       &P->pint, &P->red, &P->sched, &P->tvv, &P->kint4})
         total += (int64_t)b->bytes;
@@ -866,6 +901,18 @@ static void fill_stages(const Plan& P, int ax, FftPass& fp) {
     fp.nst = P.fft_nst[ax][0];
     for (int i = 0; i < fp.nst; ++i) fp.rad[i] = P.fft_rad[ax][i];
     fp.tw = P.tw[ax].as<float2>();
+}
+
+// support pruning of an axis-0 pass over [G0][G1][G2][C] (mode 1: stores,
+// mode 2: loads)
+static void set_xrange(const Plan& P, int C, int mode, FftPass& fp) {
+    fp.xr = P.xrange.as<int2>();
+    fp.xr_mode = mode;
+    fp.xr_G2C = P.G[2] * C;
+    fp.xr_C = C;
+    fp.xr_B1 = P.Bs[1];
+    fp.xr_B2 = P.Bs[2];
+    fp.xr_nb2 = P.nbs[2];
 }
 
 std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o) {
@@ -907,6 +954,7 @@ std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o) 
             fp.in = prev;
         }
         pass_blocking(I, &fp.Ob, &fp.Ib);
+        if (ax == 0 && d == 3 && P.xrange.p) set_xrange(P, C, 1, fp);
         out.push_back(fp);
         prev = fp.out;
         which ^= 1;
@@ -969,6 +1017,7 @@ std::vector<FftPass> adjoint_passes(Plan& P, float2* grid, float2* out, const Ad
             fp.out = dst;
             pass_blocking(I, &fp.Ob, &fp.Ib);
         }
+        if (ax == 0 && d == 3 && P.xrange.p) set_xrange(P, C, 2, fp);
         res.push_back(fp);
         cur = dst;
     }

@@ -69,6 +69,22 @@ def test_precond_parity(shape, C, M, alpha, W, kind):
     plan.close()
 
 
+def test_precond_mc_support_pruned():
+    """UTE trajectory at 64^3, 2 coils: the preconditioner's 2N plan (grid
+    160^3) skips the empty corner tiles and its one-channel adjoint FFT pass
+    loads only the support range of each column."""
+    kp = _kp()
+    shape, C = (64, 64, 64), 2
+    rng = np.random.default_rng(21)
+    k = synth.ute_3d(800, 64)
+    maps = synth.coil_maps(shape, C, rng)
+    plan = plan_for(kp, k, shape, maps, 1.25, 4)
+    pg = kp.precond_build(plan, kp.KP_PRECOND_MC).cpu().numpy()
+    po = oprecond.efficient_nufft(maps, k, shape, 1.25, 4)
+    assert rel(pg, po) < 1e-4
+    plan.close()
+
+
 @pytest.mark.parametrize("pk", ["none", "sc", "mc"])
 def test_lambda_max_parity(pk):
     kp = _kp()
