@@ -307,6 +307,9 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
     __syncthreads();
     if (base < 0) return;
     const int h2 = L / 2;
+    // scalars of the fused steps, read once (stores through a.x may alias them)
+    const float tsoft = FUSE == 1 ? *a.tau * a.lam : 0.f;
+    const float th = FUSE == 2 ? *a.theta : 0.f;
 #pragma unroll
     for (int k = 0; k < kDwtK; ++k) {
         const int r = p + k * P;
@@ -337,14 +340,14 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
             }
         }
         if (FUSE == 1 && (a.soft == 2 || r >= h2 || !olow)) {
-            const float t = *a.tau * a.lam;
-            const float m = sqrtf(acc.x * acc.x + acc.y * acc.y);
-            const float f = m > t ? 1.f - t / m : 0.f;
+            // v max(1 - t/|v|, 0), as 1 - t rsqrt(|v|^2) when |v| > t
+            const float t = tsoft;
+            const float m2 = acc.x * acc.x + acc.y * acc.y;
+            const float f = m2 > t * t ? 1.f - t * rsqrtf(m2) : 0.f;
             acc = make_float2(acc.x * f, acc.y * f);
         }
         if (FUSE == 2) {
             const int e = base + r * sr;
-            const float th = *a.theta;
             const float2 xo = a.ex[e];
             a.exbar[e] = make_float2(acc.x + th * (acc.x - xo.x), acc.y + th * (acc.y - xo.y));
             a.ex[e] = acc;
