@@ -279,6 +279,10 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
         if (i < a.I) base = dwt_base(a, o, i);
     }
     const int sr = a.S[a.ax];
+    // scalars of the fused steps, read once and early (their load overlaps the
+    // row loads; stores through a.x may alias them)
+    const float tsoft = FUSE == 1 ? *a.tau * a.lam : 0.f;
+    const float th = FUSE == 2 ? *a.theta : 0.f;
     // the line lies in the approximation sub-block of the other axes (last
     // axis only; decides which coefficients are details of this level)
     bool olow = true;
@@ -307,9 +311,6 @@ __global__ void __launch_bounds__(256) k_dwt_pass(DwtArgs a) {
     __syncthreads();
     if (base < 0) return;
     const int h2 = L / 2;
-    // scalars of the fused steps, read once (stores through a.x may alias them)
-    const float tsoft = FUSE == 1 ? *a.tau * a.lam : 0.f;
-    const float th = FUSE == 2 ? *a.theta : 0.f;
 #pragma unroll
     for (int k = 0; k < kDwtK; ++k) {
         const int r = p + k * P;
