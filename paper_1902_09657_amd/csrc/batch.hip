@@ -154,10 +154,10 @@ static DescLayout desc_layout(int n, int K, int nh) {
     L.sp = take(sizeof(SpreadArgs) * n);
     L.hv = take(sizeof(int2) * std::max(nh, 1));
     L.hl = take(sizeof(int4*) * n);
-    L.sfA = take(sizeof(int64_t) * (n + 1));
-    L.sfB = take(sizeof(int64_t) * (n + 1));
-    L.saA = take(sizeof(int64_t) * (n + 1));
-    L.saB = take(sizeof(int64_t) * (n + 1));
+    L.sfA = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
+    L.sfB = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
+    L.saA = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
+    L.saB = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
     L.sit = take(sizeof(int64_t) * (n + 1));
     L.ssp = take(sizeof(int64_t) * (n + 1));
     L.total = o;
@@ -173,8 +173,8 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
     std::vector<SpreadArgs> sp(n);
     std::vector<int2> hv;
     std::vector<const int4*> hl(n);
-    std::vector<int64_t> sfA(n + 1, 0), sfB(n + 1, 0), saA(n + 1, 0), saB(n + 1, 0), sit(n + 1, 0), ssp(n + 1, 0);
-    int maxL = 0, spread_thr = 64;
+    std::vector<int64_t> sfA, sfB, saA, saB, sit(n + 1, 0), ssp(n + 1, 0);
+    int spread_thr = 64;
     size_t spread_lds = 0;
     for (int i = 0; i < n; ++i) {
         Plan& P = *B.plans[i];
@@ -209,15 +209,56 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
         sp[i] = spread_args(P, P.kint.as<float2>(), C);
         for (int h = 0; h < P.heavy_tiles; ++h) hv.push_back(make_int2(i, h));
         hl[i] = P.heavy_list.as<int4>();
-        sfA[i + 1] = sfA[i] + fft_pass_blocks(fA[i]);
-        sfB[i + 1] = sfB[i] + fft_pass_blocks(fB[i]);
-        saA[i + 1] = saA[i] + fft_pass_blocks(aA[i]);
-        saB[i + 1] = saB[i] + fft_pass_blocks(aB[i]);
         sit[i + 1] = sit[i] + (P.M * (C / 4) + 255) / 256;
         ssp[i + 1] = ssp[i] + P.nwork;
-        maxL = std::max(maxL, std::max(P.G[0], P.G[1]));
         spread_thr = std::max(spread_thr, ((spread_threads(2, P.Bs, C) + 63) / 64) * 64);
         spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C, kZMax));
+    }
+    // FFT launches per transform length: slices sorted by G, one launch per
+    // group and phase, LDS sized for the group's own length; lines longer
+    // than 206 use 16-column blocks (54 KB of LDS at 400) so that every
+    // group keeps several resident blocks per CU
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return B.plans[x]->G[0] < B.plans[y]->G[0]; });
+    struct Group { int j0, j1, L, ncw; };
+    std::vector<Group> groups;
+    for (int j = 0; j < n; ++j) {
+        const int Lj = B.plans[ord[j]]->G[0];
+        if (groups.empty() || groups.back().L != Lj) groups.push_back({j, j, Lj, Lj <= 206 ? 32 : 16});
+        groups.back().j1 = j + 1;
+    }
+    auto narrow = [](FftPass fp, int ncw) {
+        if (fp.Ob == 1 && fp.Ib == 32 && ncw == 16) fp.Ib = 16;
+        return fp;
+    };
+    {
+        std::vector<FftPass> tA(n), tB(n), tC(n), tD((size_t)n * K);
+        std::vector<int64_t> cA(2 * n + 1, 0), cB(2 * n + 1, 0), cC(2 * n + 1, 0), cD(2 * n + 1, 0);
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const Group& G = groups[g];
+            const size_t base = (size_t)G.j0 + g;  // the group's relative block-start array
+            for (int j = G.j0; j < G.j1; ++j) {
+                const int i = ord[j];
+                tA[j] = narrow(fA[i], G.ncw);
+                tB[j] = narrow(fB[i], G.ncw);
+                tC[j] = narrow(aA[i], G.ncw);
+                for (int k = 0; k < K; ++k) tD[(size_t)k * n + j] = narrow(aB[(size_t)k * n + i], G.ncw);
+                const size_t r = base + (j - G.j0);
+                cA[r + 1] = cA[r] + fft_pass_blocks(tA[j]);
+                cB[r + 1] = cB[r] + fft_pass_blocks(tB[j]);
+                cC[r + 1] = cC[r] + fft_pass_blocks(tC[j]);
+                cD[r + 1] = cD[r] + fft_pass_blocks(tD[j]);
+            }
+        }
+        fA.swap(tA);
+        fB.swap(tB);
+        aA.swap(tC);
+        aB.swap(tD);
+        sfA.swap(cA);
+        sfB.swap(cB);
+        saA.swap(cC);
+        saB.swap(cD);
     }
     const int nh = (int)hv.size();
     const DescLayout L = desc_layout(n, K, nh);
@@ -234,15 +275,25 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
     up(L.sp, sp.data(), sizeof(SpreadArgs) * n);
     up(L.hv, hv.data(), sizeof(int2) * nh);
     up(L.hl, hl.data(), sizeof(int4*) * n);
-    up(L.sfA, sfA.data(), sizeof(int64_t) * (n + 1));
-    up(L.sfB, sfB.data(), sizeof(int64_t) * (n + 1));
-    up(L.saA, saA.data(), sizeof(int64_t) * (n + 1));
-    up(L.saB, saB.data(), sizeof(int64_t) * (n + 1));
+    up(L.sfA, sfA.data(), sizeof(int64_t) * (2 * n + 1));
+    up(L.sfB, sfB.data(), sizeof(int64_t) * (2 * n + 1));
+    up(L.saA, saA.data(), sizeof(int64_t) * (2 * n + 1));
+    up(L.saB, saB.data(), sizeof(int64_t) * (2 * n + 1));
     up(L.sit, sit.data(), sizeof(int64_t) * (n + 1));
     up(L.ssp, ssp.data(), sizeof(int64_t) * (n + 1));
-    const int ncA = fA[0].Ob * fA[0].Ib, ncB = fB[0].Ob * fB[0].Ib;
-    const int ncaA = aA[0].Ob * aA[0].Ib, ncaB = aB[0].Ob * aB[0].Ib;
     const KbParams kb = B.plans[0]->kb;
+    // one launch per length group: passes [j0, j1) of a phase table, with the
+    // group's relative block starts
+    auto fft_phase = [&](size_t tab, size_t starts, const std::vector<FftPass>& t, const std::vector<int64_t>& st,
+                         size_t shift) {
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const Group& G = groups[g];
+            const size_t base = (size_t)G.j0 + g;
+            const int ng = G.j1 - G.j0;
+            launch_fft_batch((const FftPass*)(d + tab) + shift + G.j0, (const int64_t*)(d + starts) + base, ng,
+                             st[base + ng], G.L, t[shift + G.j0].Ob * t[shift + G.j0].Ib, B.cap);
+        }
+    };
 
     if (B.exec) (void)hipGraphExecDestroy(B.exec);
     if (B.graph) (void)hipGraphDestroy(B.graph);
@@ -251,17 +302,16 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
     KP_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeRelaxed));
     try {
         for (int k = 0; k < K; ++k) {
-            launch_fft_batch((const FftPass*)(d + L.fA), (const int64_t*)(d + L.sfA), n, sfA[n], maxL, ncA, B.cap);
-            launch_fft_batch((const FftPass*)(d + L.fB), (const int64_t*)(d + L.sfB), n, sfB[n], maxL, ncB, B.cap);
+            fft_phase(L.fA, L.sfA, fA, sfA, 0);
+            fft_phase(L.fB, L.sfB, fB, sfB, 0);
             launch_interp_batch((const InterpArgs*)(d + L.it) + (size_t)k * n, (const int64_t*)(d + L.sit), n, sit[n],
                                 kb, B.cap);
             launch_spread_batch((const SpreadArgs*)(d + L.sp), (const int64_t*)(d + L.ssp), n, ssp[n], spread_thr,
                                 spread_lds, kb, B.cap);
             launch_reduce_batch((const SpreadArgs*)(d + L.sp), (const int2*)(d + L.hv), (const int4* const*)(d + L.hl),
                                 nh, B.cap);
-            launch_fft_batch((const FftPass*)(d + L.aA), (const int64_t*)(d + L.saA), n, saA[n], maxL, ncaA, B.cap);
-            launch_fft_batch((const FftPass*)(d + L.aB) + (size_t)k * n, (const int64_t*)(d + L.saB), n, saB[n], maxL,
-                             ncaB, B.cap);
+            fft_phase(L.aA, L.saA, aA, saA, 0);
+            fft_phase(L.aB, L.saB, aB, saB, (size_t)k * n);
         }
     } catch (...) {
         hipGraph_t g = nullptr;
