@@ -854,8 +854,8 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
             // the W buckets of one q0 along axis 1 are consecutive, so their
             // entries form one contiguous run; the axis-1 tap of an entry
             // follows from its bucket coordinate b1
-            auto gather = [&](int idx, int t0) {
-                float wA = wl[t0 * EP + idx];
+            auto gather = [&](int idx, const float* wrow) {
+                float wA = wrow[idx];
                 if (D == 3) wA *= *reinterpret_cast<const float*>(wly + (code[idx] >> 16));
                 const float2* up = uu + (cg * CG) * EP + idx;
                 float2 uv[CG];
@@ -871,16 +871,44 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
                     }
                 }
             };
+            // the W runs of this line, walked as one sequence: a lane's trip
+            // count is its total over the runs, so a wave waits for its
+            // busiest line once per chunk instead of once per run
+            int rs[W], re[W], tot = 0;
+#pragma unroll
             for (int q0 = 0; q0 < W; ++q0) {
                 const int bb = D == 3 ? (j0 + q0) * NB1 + j1 : (j0 + q0);
-                const int e0 = bstart[bb], e1 = bstart[bb + (D == 3 ? W : 1)];
-                const int t0 = W - 1 - q0;
-                int e = e0;
-                for (; e + 1 < e1; e += 2) {
-                    gather(e, t0);
-                    gather(e + 1, t0);
+                rs[q0] = bstart[bb];
+                re[q0] = bstart[bb + (D == 3 ? W : 1)];
+                tot += re[q0] - rs[q0];
+            }
+            int e = rs[0], end = re[0];
+            const float* wrow = wl + (W - 1) * EP;  // axis-0 weight row of the current run
+            auto advance = [&]() {  // to the first entry of the next non-empty run
+                while (e == end) {
+                    e = rs[1];
+                    end = re[1];
+#pragma unroll
+                    for (int q = 1; q + 1 < W; ++q) {
+                        rs[q] = rs[q + 1];
+                        re[q] = re[q + 1];
+                    }
+                    wrow -= EP;
                 }
-                if (e < e1) gather(e, t0);
+            };
+            int it = 0;
+            for (; it + 1 < tot; it += 2) {
+                advance();
+                const int ea = e++;
+                const float* ra = wrow;
+                advance();
+                const int eb = e++;
+                gather(ea, ra);
+                gather(eb, wrow);
+            }
+            if (it < tot) {
+                advance();
+                gather(e, wrow);
             }
         }
     }
