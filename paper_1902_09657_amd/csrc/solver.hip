@@ -434,6 +434,279 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
         for (int l = levels - 1; l >= 0; --l) run_level(l);
 }
 
+// ---- 3D prox: one launch per level and direction
+// A block transforms one brick through LDS: B x B x B coefficient positions
+// of each band (analysis) or 2B x 2B x 2B image positions (synthesis).  It
+// loads the (2B + 6)^3 values its filters reach (periodic), then filters the
+// three axes in turn, so the level costs one read and one write of its
+// block instead of three.  Levels alternate between two buffers (z and a
+// scratch image), so no block reads what another block of the launch writes:
+//   analysis level l reads buffer(l - 1) (z for l = 0) and writes buffer(l),
+//   synthesis level l reads buffer(l) and writes the approximation of level
+//   l - 1 into the origin block of buffer(l - 1) (x, xbar for l = 0),
+// with buffer(l) = scratch for even l, z for odd l.  Each write lands on
+// values that an earlier launch has consumed (the low octant of a finer
+// level).
+struct Dwt3Args {
+    const float2* in;
+    float2* out;
+    int S0, S1;   // element strides of the full image (axis 2 contiguous)
+    int n[3];     // extents of this level's approximation block
+    int nb[3];    // bricks per axis
+    int soft;     // analysis: 1 = threshold the details, 2 = every coefficient
+    const float* tau;
+    float lam;
+    float2* ex;   // synthesis of level 0: x_new to ex, x_new + theta (x_new - ex_old) to exbar
+    float2* exbar;
+    const float* theta;
+};
+
+constexpr int kDwt3B = 4;
+static_assert((2 * kDwt3B + 6) * (2 * kDwt3B + 6) <= 256, "one thread per line of a brick face");
+
+__device__ __forceinline__ void dwt3_brick(const Dwt3Args& a, int* q) {
+    int r = blockIdx.x;
+    q[2] = r % a.nb[2];
+    r /= a.nb[2];
+    q[1] = r % a.nb[1];
+    q[0] = r / a.nb[1];
+}
+
+// Brick load: the (2B + 6)^3 input values into LDS, every load of the thread
+// issued before the first LDS write.  pos(axis, u) gives the element index
+// along an axis of brick row u.
+template <int IN, typename Pos>
+__device__ __forceinline__ void dwt3_load(const Dwt3Args& a, float2* buf, Pos pos) {
+    constexpr int NLD = (IN * IN * IN + 255) / 256;
+    const int tid = threadIdx.x;
+    float2 v[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int i = tid + k * 256;
+        if (i < IN * IN * IN) {
+            const int u2 = i % IN, u1 = (i / IN) % IN, u0 = i / (IN * IN);
+            v[k] = a.in[pos(0, u0) * a.S0 + pos(1, u1) * a.S1 + pos(2, u2)];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NLD; ++k)
+        if (tid + k * 256 < IN * IN * IN) buf[tid + k * 256] = v[k];
+}
+
+// analysis of one line held in registers: outputs r < B low band, r >= B high
+template <int B, int IN>
+__device__ __forceinline__ void dwt3_fwd_line(const float2* v, float2* o) {
+#pragma unroll
+    for (int r = 0; r < 2 * B; ++r) {
+        const float* f = r < B ? c_h : c_g;
+        const int k = r < B ? r : r - B;
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            acc.x += f[t] * v[2 * k + t].x;
+            acc.y += f[t] * v[2 * k + t].y;
+        }
+        o[r] = acc;
+    }
+}
+
+// synthesis of one line: v holds B + 3 low then B + 3 high coefficients
+// starting 3 before the brick's first; outputs 2B image positions
+template <int B>
+__device__ __forceinline__ void dwt3_inv_line(const float2* v, float2* o) {
+    constexpr int NB = B + 3;
+#pragma unroll
+    for (int m = 0; m < 2 * B; ++m) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int t = (m & 1) + 2 * qq;
+            const int u = (m - t) / 2 + 3;  // m - t is even
+            acc.x += c_h[t] * v[u].x + c_g[t] * v[NB + u].x;
+            acc.y += c_h[t] * v[u].y + c_g[t] * v[NB + u].y;
+        }
+        o[m] = acc;
+    }
+}
+
+// Each axis is filtered line by line in place: a thread reads its whole line
+// into registers and writes the 2B outputs over the line's first 2B entries.
+template <int B>
+__global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
+    constexpr int IN = 2 * B + 6, OB = 2 * B;
+    extern __shared__ float2 buf[];  // [IN][IN][IN]
+    int q[3];
+    dwt3_brick(a, q);
+    const int tid = threadIdx.x;
+    const float tsoft = *a.tau * a.lam;
+    const int h0 = a.n[0] / 2, h1 = a.n[1] / 2, h2 = a.n[2] / 2;
+    // input rows 2 k0 .. 2 k0 + 2B + 5 of every axis, periodic
+    dwt3_load<IN>(a, buf, [&](int ax, int u) {
+        int sidx = 2 * q[ax] * B + u;
+        if (sidx >= a.n[ax]) sidx %= a.n[ax];
+        return sidx;
+    });
+    __syncthreads();
+    float2 v[IN], o[OB];
+    if (tid < IN * IN) {  // axis 2: line (i0, i1)
+        float2* line = buf + tid * IN;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) v[j] = line[j];
+        dwt3_fwd_line<B, IN>(v, o);
+#pragma unroll
+        for (int r = 0; r < OB; ++r) line[r] = o[r];
+    }
+    __syncthreads();
+    if (tid < IN * OB) {  // axis 1: line (i0, r2)
+        float2* line = buf + (tid / OB) * IN * IN + tid % OB;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) v[j] = line[j * IN];
+        dwt3_fwd_line<B, IN>(v, o);
+#pragma unroll
+        for (int r = 0; r < OB; ++r) line[r * IN] = o[r];
+    }
+    __syncthreads();
+    if (tid < OB * OB) {  // axis 0: line (r1, r2), soft threshold, store
+        const int r1 = tid / OB, r2 = tid % OB;
+        const float2* line = buf + r1 * IN + r2;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * IN];
+        dwt3_fwd_line<B, IN>(v, o);
+        const int c1 = q[1] * B + (r1 < B ? r1 : r1 - B);
+        const int c2 = q[2] * B + (r2 < B ? r2 : r2 - B);
+        if (c1 >= h1 || c2 >= h2) return;  // past the block (last brick of an axis)
+        const int p12 = (r1 < B ? c1 : h1 + c1) * a.S1 + (r2 < B ? c2 : h2 + c2);
+#pragma unroll
+        for (int r0 = 0; r0 < OB; ++r0) {
+            const int c0 = q[0] * B + (r0 < B ? r0 : r0 - B);
+            if (c0 >= h0) continue;
+            float2 acc = o[r0];
+            if (a.soft == 2 || r0 >= B || r1 >= B || r2 >= B) {
+                const float m2 = acc.x * acc.x + acc.y * acc.y;
+                const float g = m2 > tsoft * tsoft ? 1.f - tsoft * rsqrtf(m2) : 0.f;
+                acc = make_float2(acc.x * g, acc.y * g);
+            }
+            a.out[(r0 < B ? c0 : h0 + c0) * a.S0 + p12] = acc;
+        }
+    }
+}
+
+// x[m] = sum_q h[t] a[(m - t) / 2] + g[t] d[(m - t) / 2], t = (m & 1) + 2q,
+// indices mod n / 2; the brick holds a, d at k0 - 3 .. k0 + B - 1 (B + 3 each)
+template <int B, int FUSE>
+__global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
+    constexpr int NB = B + 3, IN = 2 * NB, OB = 2 * B;
+    extern __shared__ float2 buf[];  // [IN][IN][IN] (per axis: low band u < NB, high band NB + u)
+    int q[3];
+    dwt3_brick(a, q);
+    const int tid = threadIdx.x;
+    const float th = FUSE == 2 ? *a.theta : 0.f;
+    const int hh[3] = {a.n[0] / 2, a.n[1] / 2, a.n[2] / 2};
+    dwt3_load<IN>(a, buf, [&](int ax, int u) {
+        const int h = hh[ax];
+        int kk = q[ax] * B - 3 + (u >= NB ? u - NB : u);
+        if (kk < 0 || kk >= h) kk = ((kk % h) + h) % h;
+        return (u >= NB ? h : 0) + kk;
+    });
+    __syncthreads();
+    float2 v[IN], o[OB];
+    if (tid < IN * IN) {
+        float2* line = buf + tid * IN;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) v[j] = line[j];
+        dwt3_inv_line<B>(v, o);
+#pragma unroll
+        for (int m = 0; m < OB; ++m) line[m] = o[m];
+    }
+    __syncthreads();
+    if (tid < IN * OB) {
+        float2* line = buf + (tid / OB) * IN * IN + tid % OB;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) v[j] = line[j * IN];
+        dwt3_inv_line<B>(v, o);
+#pragma unroll
+        for (int m = 0; m < OB; ++m) line[m * IN] = o[m];
+    }
+    __syncthreads();
+    if (tid < OB * OB) {
+        const int m1 = tid / OB, m2 = tid % OB;
+        const float2* line = buf + m1 * IN + m2;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * IN];
+        const int g1 = 2 * q[1] * B + m1, g2 = 2 * q[2] * B + m2;
+        if (g1 >= a.n[1] || g2 >= a.n[2]) return;
+        const int e12 = g1 * a.S1 + g2;
+        float2 xo[OB];
+        if (FUSE == 2) {  // x_old of the line, loaded before the filtering
+#pragma unroll
+            for (int m0 = 0; m0 < OB; ++m0) {
+                const int g0 = min(2 * q[0] * B + m0, a.n[0] - 1);
+                xo[m0] = a.ex[g0 * a.S0 + e12];
+            }
+        }
+        dwt3_inv_line<B>(v, o);
+#pragma unroll
+        for (int m0 = 0; m0 < OB; ++m0) {
+            const int g0 = 2 * q[0] * B + m0;
+            if (g0 >= a.n[0]) continue;
+            const int e = g0 * a.S0 + e12;
+            const float2 acc = o[m0];
+            if (FUSE == 2) {
+                a.exbar[e] = make_float2(acc.x + th * (acc.x - xo[m0].x), acc.y + th * (acc.y - xo[m0].y));
+                a.ex[e] = acc;
+            } else {
+                a.out[e] = acc;
+            }
+        }
+    }
+}
+
+static size_t dwt3_lds_bytes() {
+    constexpr int IN = 2 * kDwt3B + 6;
+    return sizeof(float2) * (size_t)(IN * IN * IN);
+}
+
+static void dwt3_prox(float2* z, float2* scratch, const int64_t* N, int levels, const DwtFuse& fz, hipStream_t s) {
+    if (N[0] * N[1] * N[2] >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "wavelet: image too large");
+    auto level_buf = [&](int l) { return (l % 2 == 0) ? scratch : z; };
+    auto args = [&](int l) {
+        Dwt3Args a{};
+        a.S0 = (int)(N[1] * N[2]);
+        a.S1 = (int)N[2];
+        for (int b = 0; b < 3; ++b) {
+            a.n[b] = (int)(N[b] >> l);
+            a.nb[b] = (a.n[b] / 2 + kDwt3B - 1) / kDwt3B;
+        }
+        return a;
+    };
+    const size_t lds = dwt3_lds_bytes();
+    for (int l = 0; l < levels; ++l) {
+        Dwt3Args a = args(l);
+        a.in = l == 0 ? z : level_buf(l - 1);
+        a.out = level_buf(l);
+        a.soft = l == levels - 1 ? 2 : 1;
+        a.tau = fz.tau;
+        a.lam = fz.lam;
+        hipLaunchKernelGGL(k_dwt3_analysis<kDwt3B>, dim3((unsigned)(a.nb[0] * a.nb[1] * a.nb[2])), dim3(256), lds, s, a);
+        KP_LAUNCH_CHECK();
+    }
+    for (int l = levels - 1; l >= 0; --l) {
+        Dwt3Args a = args(l);
+        a.in = level_buf(l);
+        const dim3 grid((unsigned)(a.nb[0] * a.nb[1] * a.nb[2]));
+        if (l == 0) {
+            a.ex = fz.ex;
+            a.exbar = fz.exbar;
+            a.theta = fz.theta;
+            hipLaunchKernelGGL((k_dwt3_synthesis<kDwt3B, 2>), grid, dim3(256), lds, s, a);
+        } else {
+            a.out = level_buf(l - 1);
+            hipLaunchKernelGGL((k_dwt3_synthesis<kDwt3B, 0>), grid, dim3(256), lds, s, a);
+        }
+        KP_LAUNCH_CHECK();
+    }
+}
+
 // ------------------------------------------------------------- total variation
 // G: periodic forward differences along every axis, (G x)_a[n] = x[n + e_a] - x[n];
 // G^H v = sum_a v_a[n - e_a] - v_a[n].  The dual variable is stored [d][N].
@@ -752,8 +1025,12 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
             // analysis passes, x, xbar <- x_new, x_new + theta (x_new - x)
             // into the last synthesis pass (levels >= 1 was checked)
             DwtFuse fz{tau + k, op.lambda, x, xbar, th + k};
-            dwt(z, P.N, P.d, levels, false, s, &fz);
-            dwt(z, P.N, P.d, levels, true, s, &fz);
+            if (P.d == 3) {
+                dwt3_prox(z, P.img[3].as<float2>(), P.N, levels, fz, s);
+            } else {
+                dwt(z, P.N, P.d, levels, false, s, &fz);
+                dwt(z, P.N, P.d, levels, true, s, &fz);
+            }
         }
         if (op.objective_host) op.objective_host[k + 1] = objective(P, x, yint, op.reg, op.lambda, levels, s);
     }

@@ -120,6 +120,9 @@ SOLVE_CASES = [
     # one level: every coefficient is thresholded after the first level's last axis
     ((24, 32), 3, 2000, 1.25, 4, "l1wav", 5e-3, "mc", 10, 1),
     ((16, 16, 16), 2, 3000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 1),
+    # 3D bricks of 4 coefficients per band cut short at the block edge (10, 6,
+    # 5, 3 per band), the deepest level shorter than the filter on every axis
+    ((40, 24, 16), 2, 4000, 1.25, 4, "l1wav", 5e-3, "mc", 8, 3),
 ]
 
 
