@@ -123,6 +123,8 @@ SOLVE_CASES = [
     # 3D bricks of 4 coefficients per band cut short at the block edge (10, 6,
     # 5, 3 per band), the deepest level shorter than the filter on every axis
     ((40, 24, 16), 2, 4000, 1.25, 4, "l1wav", 5e-3, "mc", 8, 3),
+    # deepest level two samples long on axis 0 (one coefficient per band)
+    ((8, 16, 16), 2, 2000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 3),
 ]
 
 
