@@ -396,6 +396,9 @@ def main():
     ap.add_argument("--profile-stages", type=int, default=0, metavar="R",
                     help="counter-collection mode: build the plan, run each NUFFT stage R times and a plain copy of "
                          "512 MiB (read) + 512 MiB (write) for calibration, then exit without a JSON line")
+    ap.add_argument("--form-only", choices=["batched", "differentiable"], default=None,
+                    help="profiling mode: run only that form's measurement and print its JSON object (no headline "
+                         "line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the per-GPU share is the "
@@ -408,6 +411,10 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.form_only:
+        fn = bench_batched if args.form_only == "batched" else bench_differentiable
+        print(json.dumps(fn(kp, dev)), flush=True)
+        return
     cfg = synth.config(3)
     d = cfg.ndim
     log("generating inputs", cfg.name)

@@ -57,7 +57,10 @@ enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1, KP_REG_TV = 2 };
  * own tiles (spread_bin_size), through per-tile touch lists. */
 typedef struct {
     int bin_size[3];        /* sort / interpolation tile edge per axis; divides G_a */
-    int max_chunk;          /* max touch-list entries per spreading work item        */
+    int max_chunk;          /* max touch-list entries per spreading work item; 0:
+                               1024 for plans of 4096 x 1024 entries and more, else
+                               halved (down to 128) until the plan has that many
+                               items' worth                                          */
     int spread_bin_size[3]; /* spreading tile edge per axis; divides G_a; last axis
                                <= 8; in 3D axis 1 + W <= 65 (else
                                KP_ERR_UNSUPPORTED)                                   */

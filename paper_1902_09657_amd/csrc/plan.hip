@@ -604,7 +604,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     P->spread_lds = (int)spread_lds_bytes(ndim, kb_width, P->Bs, C);
     if (P->spread_lds > P->lds_max) fail(KP_ERR_UNSUPPORTED, "spreading chunk does not fit in LDS");
     if (P->nbins >= ((int64_t)1 << 31) || P->nstiles >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "too many tiles");
-    const int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 1024;
+    int max_chunk = (tuning && tuning->max_chunk > 0) ? tuning->max_chunk : 0;  // 0: chosen below
 
     const int64_t M = nsamples;
     const int d = ndim;
@@ -709,6 +709,16 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
             const int2 r = xr[(size_t)ty * nb2 + tz];
             skip[t] = (tx * P->Bs[0] >= r.y || (tx + 1) * P->Bs[0] <= r.x) ? 1 : 0;
         }
+    }
+    // Built-in split size: 1024 entries when the plan has work for thousands
+    // of such items, halved down to one chunk otherwise.  A small plan (a 2D
+    // slice) has too few tiles to fill the GPU, so its time is the longest
+    // work item's chain of chunks; a large one (3D) is throughput bound, where
+    // fewer, longer items cost fewer partial tiles.
+    if (max_chunk == 0) {
+        const int64_t entries = toff[P->nstiles];
+        max_chunk = 1024;
+        while (max_chunk > kSpreadChunk && entries < (int64_t)4096 * max_chunk) max_chunk /= 2;
     }
     std::vector<int4> heavy_items, light_items;
     std::vector<int4> heavy;  // (tile, first slot, slots, 0)
