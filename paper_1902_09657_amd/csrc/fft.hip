@@ -623,6 +623,10 @@ bool fft_fixed_ok(int L, int nc) {
 void launch_fft_pass(const FftPass& pin, hipStream_t s) {
     FftPass p = pin;
     const int lim = lds_limit();
+    // a small transform (a 2D slice) has too few 32-column blocks to fill the
+    // GPU: narrower blocks (16, 8 columns) until the pass has 1024 of them
+    if (p.Ob == 1 && p.Ib == 32 && p.xr_mode == 0 && p.pre != PRE_MAPS && p.post != POST_MAPS)
+        while (p.Ib > 8 && fft_pass_blocks(p) < 1024) p.Ib /= 2;
     if (launch_fixed(p, s, lim)) return;
     // support-pruned loads exist only in the specialised kernel
     if (p.xr_mode == 2) fail(KP_ERR_UNSUPPORTED, "support-pruned FFT pass needs the specialised kernel");
