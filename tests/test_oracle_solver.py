@@ -1,5 +1,6 @@
 """Pins for the oracle's preconditioner, wavelet, PDHG and unrolled gradient."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -98,6 +99,15 @@ def test_db4_orthonormal_and_vanishing_moments():
     for m in range(4):
         assert abs(np.sum(g * t ** m)) < 1e-9 * max(1, 8 ** m)
     assert abs(np.sum(h) - math.sqrt(2)) < 1e-15
+
+
+def test_db4_matches_published_table():
+    """The derived filter equals Daubechies' printed N = 4 coefficients (16 decimals)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "db4_lowpass_daubechies.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    ref = np.array([float(v) for _, v in rows])
+    assert [int(i) for i, _ in rows] == list(range(8))
+    np.testing.assert_allclose(wavelet.db4_filter(), ref, rtol=0, atol=1e-15)
 
 
 @pytest.mark.parametrize("shape,levels", [((16,), 2), ((16, 8), 2), ((8, 8, 16), 2)])
