@@ -326,6 +326,13 @@ def pdhg_solve_batch(batch: Batch, y, p=None, lam=1e-3, iters=20, lambda_max=0.0
     if p is not None:
         p = [_dev(t, torch.float32, "p") for t in p]
         kind = _p_kind(p[0])
+        # one preconditioner kind for the whole batch: every p must be [M_i]
+        # (single-channel) or every p [C, M_i] (multi-channel)
+        for i, (t, m) in enumerate(zip(p, batch.nsamples)):
+            want = (m,) if kind == KP_PRECOND_SC else (batch.ncoils, m)
+            if tuple(t.shape) != want:
+                raise ValueError("p[%d] has shape %s, expected %s (all slices need the same preconditioner kind)"
+                                 % (i, tuple(t.shape), want))
     o = PdhgOpts()
     o.reg = KP_REG_L2
     o.lam = float(lam)

@@ -215,6 +215,62 @@ def test_batched_workload_slices():
     b.close()
 
 
+
+def test_batched_workload_all_64_slices():
+    """The whole 64-slice batch, one pdhg_solve_batch as the benchmark times it:
+    every slice equals its plain per-slice solve (itself held to the oracle),
+    and two sampled slices (one per grid length 160 and 240) equal the FP64
+    oracle.  The sampled slices take their data, preconditioner and lambda_max
+    from the oracle side only; every slice uses the single-channel
+    preconditioner, since one batch call takes one preconditioner kind."""
+    kp = _kp()
+    C, K, lam = 12, 20, 1e-3
+    sl = synth.slice_config4(64, seed=4, ncoils=C)
+    pick = [[i for i, (s, _) in enumerate(sl) if s[0] == n][0] for n in (128, 192)]
+    coords, maps_l, ys, ps, lms, plans, ops = [], [], [], [], [], [], {}
+    print("batched 64 slices, oracle-sampled", pick, flush=True)
+    for i, (shape, k) in enumerate(sl):
+        rp, rm, _, rn = synth.streams(4000 + i)
+        x = synth.phantom(shape, rp)
+        m = synth.coil_maps(shape, C, rm)
+        kt, mt = dev(k, torch.float32), dev(m, torch.complex64)
+        pl = _plan(kp, k, shape, m, 1.25, 4)
+        if i in pick:
+            op = onufft.Nufft(k, shape, m, 1.25, 4)
+            y = op.forward(x) + synth.noise((C, k.shape[0]), 1e-3, rn)
+            p = oprecond.efficient_nufft(None, k, shape, 1.25, 4)[0]
+            ops[i] = (op, y, p)
+            yt, pt = dev(y, torch.complex64), dev(p, torch.float32)
+        else:
+            yt = dev(synth.noise((C, k.shape[0]), 1.0, rn), torch.complex64)
+            pt = kp.precond_build(pl, kp.KP_PRECOND_SC)   # one kind per batch
+        coords.append(kt)
+        maps_l.append(mt)
+        ys.append(yt)
+        ps.append(pt)
+        lms.append(1.5)
+        plans.append(pl)
+    b = kp.nufft_plan_batch(coords, [s for s, _ in sl], maps_l, oversamp=1.25, kb_width=4, tune=True)
+    assert all(kp.nufft_batch_info(b, j)["fast"] for j in range(len(sl)))
+    with pytest.raises(ValueError):   # mixed preconditioner kinds are refused
+        kp.pdhg_solve_batch(b, ys, ps[:1] + [p.expand(C, -1).contiguous() for p in ps[1:]], lam=lam, iters=K, lambda_max=lms)
+    xb = kp.pdhg_solve_batch(b, ys, ps, lam=lam, iters=K, lambda_max=lms)
+    worst = 0.0
+    for i, pl in enumerate(plans):
+        xp = kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=lam, iters=K, lambda_max=lms[i])
+        worst = max(worst, rel(xb[i].cpu().numpy(), xp.cpu().numpy()))
+        pl.close()
+    print("batch vs plain, worst rel", worst, flush=True)
+    assert worst < 1e-5
+    for i in pick:
+        op, y, p = ops[i]
+        xo, _, _ = opdhg.pdhg(op.forward, op.adjoint, y, p, sl[i][0], "l2", lam, K, lmax=1.5)
+        r = rel(xb[i].cpu().numpy(), xo)
+        print("slice", i, sl[i][0], "rel vs oracle", r, flush=True)
+        assert r < 1e-4
+    b.close()
+
+
 def test_differentiable_workload_slice():
     from paper_1902_09657_amd.autograd import UnrolledPdhg, schedule_params
     kp = _kp()
