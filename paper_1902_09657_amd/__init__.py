@@ -39,6 +39,28 @@ def _dev(t, dtype, name):
     return t.contiguous()
 
 
+def _numel(t, n, name):
+    """Refuse a buffer whose size differs from what the library will read or
+    write through its pointer (the C-ABI takes bare pointers)."""
+    if t is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return t
+
+
+def _p_numel(p, ncoils, nsamples):
+    """p is [M] (single-channel) or [C, M] (multi-channel)."""
+    if p is not None:
+        _numel(p, nsamples if p.dim() == 1 else ncoils * nsamples, "p")
+    return p
+
+
+def _nimg(shape):
+    n = 1
+    for v in shape:
+        n *= int(v)
+    return n
+
+
 class Plan:
     """A NUFFT plan (owns the library handle); see nufft_plan."""
 
@@ -124,17 +146,19 @@ def nufft_plan(coords, shape, maps=None, oversamp=1.25, kb_width=4, bin_size=Non
 
 
 def nufft_forward(plan: Plan, x, out=None):
-    x = _dev(x, torch.complex64, "x")
+    x = _numel(_dev(x, torch.complex64, "x"), _nimg(plan.shape), "x")
     if out is None:
         out = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device)
+    _numel(out, plan.ncoils * plan.nsamples, "out")
     _lib.check(_lib.load().nufft_forward(plan.handle, _ptr(x), _ptr(out), _stream()))
     return out
 
 
 def nufft_adjoint(plan: Plan, y, out=None):
-    y = _dev(y, torch.complex64, "y")
+    y = _numel(_dev(y, torch.complex64, "y"), plan.ncoils * plan.nsamples, "y")
     if out is None:
         out = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
+    _numel(out, _nimg(plan.shape), "out")
     _lib.check(_lib.load().nufft_adjoint(plan.handle, _ptr(y), _ptr(out), _stream()))
     return out
 
@@ -155,7 +179,7 @@ def _p_kind(p):
 def pdhg_lambda_max(plan: Plan, p=None, iters=30):
     out = torch.empty(1, dtype=torch.float32, device=plan.device)
     if p is not None:
-        p = _dev(p, torch.float32, "p")
+        p = _p_numel(_dev(p, torch.float32, "p"), plan.ncoils, plan.nsamples)
     _lib.check(_lib.load().pdhg_lambda_max(plan.handle, _ptr(p), _p_kind(p), int(iters), _ptr(out), _stream()))
     return out
 
@@ -165,9 +189,9 @@ def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_leve
                lambda_max_out=None):
     """Run the preconditioned PDHG (reg "l2", "l1wav" or "tv").  Returns x (and u,
     objective history when asked)."""
-    y = _dev(y, torch.complex64, "y")
+    y = _numel(_dev(y, torch.complex64, "y"), plan.ncoils * plan.nsamples, "y")
     if p is not None:
-        p = _dev(p, torch.float32, "p")
+        p = _p_numel(_dev(p, torch.float32, "p"), plan.ncoils, plan.nsamples)
     o = PdhgOpts()
     regs = {"l2": KP_REG_L2, "l1wav": KP_REG_L1_WAVELET, "tv": KP_REG_TV}
     if reg not in regs:
@@ -181,9 +205,9 @@ def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_leve
     o.sigma0 = float(sigma0)
     o.accel = 1 if accel else 0
     if x0 is not None:
-        x0 = _dev(x0, torch.complex64, "x0")
+        x0 = _numel(_dev(x0, torch.complex64, "x0"), _nimg(plan.shape), "x0")
     if u0 is not None:
-        u0 = _dev(u0, torch.complex64, "u0")
+        u0 = _numel(_dev(u0, torch.complex64, "u0"), plan.ncoils * plan.nsamples, "u0")
     o.x0 = _ptr(x0).value
     o.u0 = _ptr(u0).value
     hist = None
@@ -207,9 +231,9 @@ def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_leve
 def l2_dual_cg(plan: Plan, y, p=None, lam=1e-3, iters=50, want_u=False, residuals=False):
     """l2 reconstruction through its dual: preconditioned CG on (A A^H + lam I) u = lam y,
     x = A^H u / lam.  Returns x (and u, relative residual history when asked)."""
-    y = _dev(y, torch.complex64, "y")
+    y = _numel(_dev(y, torch.complex64, "y"), plan.ncoils * plan.nsamples, "y")
     if p is not None:
-        p = _dev(p, torch.float32, "p")
+        p = _p_numel(_dev(p, torch.float32, "p"), plan.ncoils, plan.nsamples)
     x = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
     u = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device) if want_u else None
     hist = (ctypes.c_double * (int(iters) + 1))() if residuals else None
@@ -321,7 +345,8 @@ def pdhg_solve_batch(batch: Batch, y, p=None, lam=1e-3, iters=20, lambda_max=0.0
     n = len(batch)
     if len(y) != n or (p is not None and len(p) != n):
         raise ValueError("y and p must have one entry per slice")
-    y = [_dev(t, torch.complex64, "y") for t in y]
+    y = [_numel(_dev(t, torch.complex64, "y"), batch.ncoils * m, "y[%d]" % i)
+         for i, (t, m) in enumerate(zip(y, batch.nsamples))]
     kind = KP_PRECOND_NONE
     if p is not None:
         p = [_dev(t, torch.float32, "p") for t in p]

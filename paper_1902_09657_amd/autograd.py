@@ -13,7 +13,7 @@ import math
 import torch
 
 from . import _lib
-from . import Plan, PdhgOpts, nufft_adjoint, nufft_forward, _p_kind, _ptr, _stream, _dev
+from . import Plan, PdhgOpts, nufft_adjoint, nufft_forward, _p_kind, _ptr, _stream, _dev, _numel, _p_numel, _nimg
 
 
 class SenseNufft(torch.autograd.Function):
@@ -62,14 +62,14 @@ class UnrolledPdhg(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y, params, plan: Plan, p, K: int, ckpt_every: int, x0=None):
         L = _lib.load()
-        y = _dev(y, torch.complex64, "y")
+        y = _numel(_dev(y, torch.complex64, "y"), plan.ncoils * plan.nsamples, "y")
         params = _dev(params, torch.float32, "params")
         if params.numel() != 3 * K + 1:
             raise ValueError("params must hold 3K+1 values")
         if p is not None:
-            p = _dev(p, torch.float32, "p")
+            p = _p_numel(_dev(p, torch.float32, "p"), plan.ncoils, plan.nsamples)
         if x0 is not None:
-            x0 = _dev(x0, torch.complex64, "x0")
+            x0 = _numel(_dev(x0, torch.complex64, "x0"), _nimg(plan.shape), "x0")
         nbytes = L.pdhg_unrolled_ckpt_bytes(plan.handle, int(K), int(ckpt_every))
         if nbytes <= 0:
             raise ValueError("invalid K / ckpt_every")
@@ -92,7 +92,7 @@ class UnrolledPdhg(torch.autograd.Function):
         rest = saved[3:]
         p = rest.pop(0) if ctx.has_p else None
         x0 = rest.pop(0) if ctx.has_x0 else None
-        gx = gx.contiguous().to(torch.complex64)
+        gx = _numel(gx.contiguous().to(torch.complex64), _nimg(ctx.plan.shape), "grad of x")
         g_params = torch.empty_like(params)
         g_y = torch.empty_like(y)
         g_x0 = torch.empty(ctx.plan.shape, dtype=torch.complex64, device=y.device) if ctx.has_x0 else None
@@ -114,7 +114,7 @@ def schedule_params(plan: Plan, p=None, K=10, lam=1e-3, lambda_max=0.0, sigma0=1
     the initial value of learnable unrolled parameters."""
     import ctypes
     if p is not None:
-        p = _dev(p, torch.float32, "p")
+        p = _p_numel(_dev(p, torch.float32, "p"), plan.ncoils, plan.nsamples)
     o = PdhgOpts()
     o.reg = _lib.KP_REG_L2
     o.lam = float(lam)

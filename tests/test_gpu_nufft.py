@@ -219,3 +219,29 @@ def test_edge_cases():
     op = onufft.Nufft(k2, shape, None, 2.0, 4)
     assert rel(kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy(), op.forward(x)) < 1e-4
     plan.close()
+
+
+def test_wrong_sized_buffers_refused():
+    """Buffers whose size differs from the plan's are refused on the host,
+    before any launch (the C-ABI only sees bare pointers)."""
+    kp = _kp()
+    rng = np.random.default_rng(7)
+    shape, C, M = (16, 16), 2, 300
+    k = rng.uniform(-math.pi, math.pi, (M, 2)).astype(np.float32)
+    maps = rng.standard_normal((C,) + shape) + 1j * rng.standard_normal((C,) + shape)
+    plan = _plan(kp, k, shape, maps, 1.25, 4)
+    x_bad = dev(np.zeros((16, 15)), torch.complex64)
+    y_bad = dev(np.zeros((C, M - 1)), torch.complex64)
+    y = dev(np.zeros((C, M)), torch.complex64)
+    p_bad = dev(np.ones(M + 1), torch.float32)
+    for call in (lambda: kp.nufft_forward(plan, x_bad),
+                 lambda: kp.nufft_adjoint(plan, y_bad),
+                 lambda: kp.pdhg_solve(plan, y_bad, iters=1, lambda_max=1.0),
+                 lambda: kp.pdhg_solve(plan, y, p_bad, iters=1, lambda_max=1.0),
+                 lambda: kp.pdhg_solve(plan, y, iters=1, lambda_max=1.0, x0=x_bad),
+                 lambda: kp.pdhg_lambda_max(plan, p_bad),
+                 lambda: kp.l2_dual_cg(plan, y, p_bad, iters=1)):
+        with pytest.raises(ValueError):
+            call()
+    torch.cuda.synchronize()
+    plan.close()

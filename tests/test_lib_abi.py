@@ -76,3 +76,20 @@ def test_library_db4_matches_oracle():
     h = (ctypes.c_double * 8)()
     assert L.load().kp_db4_filter(h) == 0
     np.testing.assert_allclose(np.array(h[:]), wavelet.db4_filter(), rtol=0, atol=1e-13)
+
+
+def test_binding_size_checks():
+    """The binding's size checks (host only: CPU tensors)."""
+    import torch
+    from paper_1902_09657_amd import _numel, _p_numel, _nimg
+    assert _nimg((4, 5, 6)) == 120
+    t = torch.zeros(3, 7)
+    assert _numel(t, 21, "t") is t
+    with pytest.raises(ValueError):
+        _numel(t, 20, "t")
+    assert _p_numel(torch.zeros(7), 3, 7) is not None          # single-channel [M]
+    assert _p_numel(torch.zeros(3, 7), 3, 7) is not None       # multi-channel [C, M]
+    with pytest.raises(ValueError):
+        _p_numel(torch.zeros(21), 3, 7)                        # flat [C*M] read as [M]
+    with pytest.raises(ValueError):
+        _p_numel(torch.zeros(2, 7), 3, 7)
