@@ -93,3 +93,22 @@ def test_binding_size_checks():
         _p_numel(torch.zeros(21), 3, 7)                        # flat [C*M] read as [M]
     with pytest.raises(ValueError):
         _p_numel(torch.zeros(2, 7), 3, 7)
+
+
+def test_missing_library_fails_loudly():
+    """No fallback: a missing shared library is an error, not a slower path."""
+    import subprocess
+    import sys
+    code = ("from paper_1902_09657_amd import _lib\n"
+            "try:\n    _lib.load('/nonexistent/libkpdhg.so')\nexcept ImportError:\n    print('raised')\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert out.stdout.strip() == "raised", out.stderr
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1902_09657_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
