@@ -293,7 +293,10 @@ int nufft_batch_info(kp_batch_t batch, int slice, kp_plan_info* info, int* fast)
 /* l2-regularised PDHG (as pdhg_solve with reg = KP_REG_L2, no x0, u0 or
  * objective) on every slice: y, p and x_out are host arrays of nslices
  * device pointers with the per-slice layouts of pdhg_solve (p may be NULL
- * for KP_PRECOND_NONE).  Each slice gets its own step schedule from its
+ * for KP_PRECOND_NONE).  p_kind applies to every slice: each p[i] must hold
+ * M_i floats (SC) or C * M_i floats (MC); the library cannot check the
+ * sizes behind the pointers, so a shorter buffer is read out of bounds.
+ * Each slice gets its own step schedule from its
  * own lambda_max: lambda_max[i] (host float [nslices], each > 0) when the
  * array is given, else opts->lambda_max when > 0, else the power method on
  * that slice.  The K iterations are
