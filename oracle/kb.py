@@ -16,9 +16,12 @@ Its continuous Fourier transform, used for deapodisation:
 
     Chat(nu) = sinh( sqrt(beta^2 - (pi W nu)^2) ) / sqrt(beta^2 - (pi W nu)^2)
 
-Pins: Chat against numerical quadrature of C (tests/test_oracle_operators.py); beta
-and C through the NUFFT-vs-NDFT accuracy pins, which fail for a wrong beta or
-kernel normalisation.
+Pins (tests/test_oracle_operators.py): Chat against numerical quadrature of
+C; beta at alpha = 2 and 1.25 (W = 4) against the published formula
+evaluated by hand; beta gives a smaller NUFFT-vs-NDFT error than 5 % and
+10 % above or below it and than the formula without its -0.8 term (the
+property Beatty et al. chose it for); the NUFFT-vs-NDFT errors within 1.25x
+of their measured values.
 """
 from __future__ import annotations
 

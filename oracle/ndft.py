@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Problem Setup, Eq. (model_i) and Eq. (model), written in d dimensions as the
-paper allows ("for notation simplicity, we focus on one-dimensional signals"):
+Problem Setup, Eq. (model_i) and Eq. (model), written in d dimensions (the
+paper states the model for one dimension only to keep the notation short):
 
     y_c[i] = N^{-1/2} sum_n s_c[n] x[n] exp(-i omega_i . n)
     x[n]   = N^{-1/2} sum_c conj(s_c[n]) sum_i y_c[i] exp(+i omega_i . n)

@@ -25,10 +25,14 @@ of W x.
 
 Complex soft threshold: soft(v, t) = v max(1 - t/|v|, 0), and 0 at v = 0.
 
-Pins: the defining identity |H(e^{i xi})|^2 = 2 cos^8(xi/2) P(sin^2(xi/2))
-at random xi; orthonormality and double-shift orthogonality; four vanishing
-moments; W^T W = I as a dense matrix; perfect reconstruction
-(tests/test_oracle_solver.py).
+Pins (tests/test_oracle_solver.py): Daubechies' published N = 4 table; the
+defining identity |H(e^{i xi})|^2 = 2 cos^8(xi/2) P(sin^2(xi/2)) at random
+xi; orthonormality and double-shift orthogonality; four vanishing moments;
+W^T W = I as a dense matrix; the multi-level pyramid against an independent
+product of dense per-level Kronecker matrices (1D/2D/3D, 2-4 levels); a
+constant gives zero details at every level and a coarsest approximation of
+c 2^(dL/2); a cubic gives zero details at every level away from the wrap;
+level l is the one-level transform of level l - 1's approximation block.
 """
 from __future__ import annotations
 

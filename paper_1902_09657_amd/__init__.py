@@ -215,6 +215,14 @@ def pdhg_solve(plan: Plan, y, p=None, reg="l2", lam=1e-3, iters=20, wavelet_leve
         hist = (ctypes.c_double * (iters + 1))()
         o.objective_host = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
     if lambda_max_out is not None:
+        # written in place through its pointer: a device float32 tensor of at
+        # least one element, used as given (not a contiguous copy)
+        if not isinstance(lambda_max_out, torch.Tensor) or not lambda_max_out.is_cuda:
+            raise TypeError("lambda_max_out must be a CUDA (HIP) tensor")
+        if lambda_max_out.dtype != torch.float32:
+            raise TypeError("lambda_max_out must be torch.float32")
+        if lambda_max_out.numel() < 1:
+            raise ValueError("lambda_max_out must hold at least one element")
         o.lambda_max_out = lambda_max_out.data_ptr()
     x = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
     u = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device) if want_u else None

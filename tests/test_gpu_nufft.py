@@ -243,5 +243,15 @@ def test_wrong_sized_buffers_refused():
                  lambda: kp.l2_dual_cg(plan, y, p_bad, iters=1)):
         with pytest.raises(ValueError):
             call()
+    # lambda_max_out is written in place through its pointer: a host tensor,
+    # a wrong dtype or an empty tensor is refused before the solve starts
+    for bad, exc in ((torch.zeros(1, dtype=torch.float32), TypeError),
+                     (torch.zeros(1, dtype=torch.float64, device="cuda"), TypeError),
+                     (torch.zeros(0, dtype=torch.float32, device="cuda"), ValueError)):
+        with pytest.raises(exc):
+            kp.pdhg_solve(plan, y, iters=1, lambda_max_out=bad)
+    lm = torch.zeros(1, dtype=torch.float32, device="cuda")
+    kp.pdhg_solve(plan, y, iters=1, lambda_max=1.5, lambda_max_out=lm)
+    assert float(lm.item()) == 1.5
     torch.cuda.synchronize()
     plan.close()

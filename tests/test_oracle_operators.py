@@ -102,17 +102,33 @@ def test_sos_invariant_full_cartesian_is_identity():
     np.testing.assert_allclose(A.conj().T @ A, np.eye(64), atol=1e-6)
 
 
+def test_kb_beta_values():
+    """Beatty et al.'s shape parameter (cited in Experiments) at the two
+    oversampling ratios used here, evaluated by hand from their published
+    formula: pi sqrt(2^2 1.5^2 - 0.8) = pi sqrt(8.2) and
+    pi sqrt(3.2^2 0.75^2 - 0.8) = pi sqrt(4.96)."""
+    assert abs(kb.kb_beta(2.0, 4) - 8.996152) < 1e-6
+    assert abs(kb.kb_beta(1.25, 4) - 6.996659) < 1e-6
+
+
 # --------------------------------------------------------- gridding NUFFT
-THRESH = {(2.0, 4): 1.3e-3, (1.25, 4): 1.4e-2, (2.0, 6): 2e-5, (1.25, 6): 9e-4, (2.0, 8): 4e-6}
+# measured errors of this fixed case: 6.51e-4, 7.29e-3, 7.47e-6, 4.50e-4,
+# 1.64e-6; each bound is 1.25x its measurement, so a kernel whose shape
+# parameter lacks Beatty's -0.8 correction (errors 1.35-2x larger) fails
+THRESH = {(2.0, 4): 8.2e-4, (1.25, 4): 9.2e-3, (2.0, 6): 9.4e-6, (1.25, 6): 5.7e-4, (2.0, 8): 2.1e-6}
 
 
-def test_nufft_converges_to_ndft():
+def _ndft_case():
     rng = np.random.default_rng(0)
     shape = (32, 32)
     k = synth.random_coords(2000, 2, rng)
     k[8:58] = 0.0                       # 50 samples exactly at the centre
     x = _rand_c(rng, shape)
-    ye = ndft.forward(x, None, k, shape)
+    return shape, k, x, ndft.forward(x, None, k, shape)
+
+
+def test_nufft_converges_to_ndft():
+    shape, k, x, ye = _ndft_case()
     errs = {}
     for (a, W), th in THRESH.items():
         y = nufft.Nufft(k, shape, None, a, W).forward(x)
@@ -120,6 +136,27 @@ def test_nufft_converges_to_ndft():
         assert errs[(a, W)] < th, ((a, W), errs[(a, W)])
     assert errs[(2.0, 8)] < errs[(2.0, 6)] < errs[(2.0, 4)]
     assert errs[(1.25, 6)] < errs[(1.25, 4)]
+
+
+@pytest.mark.parametrize("alpha,W", [(2.0, 4), (1.25, 4), (1.25, 6)])
+def test_kb_beta_is_near_optimal(alpha, W, monkeypatch):
+    """Beatty et al. chose beta to minimise the gridding error; the oracle's
+    beta gives a smaller NUFFT-vs-NDFT error than 5 % or 10 % above or below
+    it, and than the same formula without its -0.8 correction."""
+    shape, k, x, ye = _ndft_case()
+    beta0 = kb.kb_beta(alpha, W)
+
+    def err(beta):
+        monkeypatch.setattr(kb, "kb_beta", lambda a, w: beta)
+        y = nufft.Nufft(k, shape, None, alpha, W).forward(x)
+        monkeypatch.undo()
+        return np.linalg.norm(y - ye) / np.linalg.norm(ye)
+
+    e0 = err(beta0)
+    for f in (0.9, 0.95, 1.05, 1.1):
+        assert e0 < err(beta0 * f), f
+    a = float(np.float32(alpha))
+    assert e0 < err(math.pi * (W / a) * (a - 0.5)) / 1.3
 
 
 def test_nufft_3d_multicoil_matches_ndft():

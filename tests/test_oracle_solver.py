@@ -127,6 +127,97 @@ def test_wavelet_polynomial_has_zero_details():
     assert np.max(np.abs(d[:28])) < 1e-12
 
 
+def _band_mask(shape, levels):
+    """True on the coarsest approximation block, False on every detail band."""
+    m = np.zeros(shape, bool)
+    m[tuple(slice(0, n >> levels) for n in shape)] = True
+    return m
+
+
+@pytest.mark.parametrize("shape,levels", [((64,), 4), ((32, 16), 2), ((32, 16), 3), ((16, 16, 32), 3),
+                                          ((16, 16, 16), 4)])
+def test_wavelet_constant_multilevel(shape, levels):
+    """A constant c: every detail band of every level is zero (the filter has
+    vanishing moments and the constant is periodic), and the coarsest
+    approximation equals c 2^(d L / 2) (each level and axis multiplies it by
+    sum h = sqrt 2).  Transforming anything but the approximation block at a
+    level breaks both."""
+    c = 0.7 - 0.3j
+    out = wavelet.forward(np.full(shape, c), levels)
+    m = _band_mask(shape, levels)
+    np.testing.assert_allclose(out[m], c * 2.0 ** (len(shape) * levels / 2), rtol=1e-13)
+    assert np.max(np.abs(out[~m])) < 1e-12
+    np.testing.assert_allclose(wavelet.inverse(out, levels), np.full(shape, c), atol=1e-13)
+
+
+def test_wavelet_cubic_details_zero_at_every_level():
+    """A cubic along a 1D signal: away from the periodic wrap, the details of
+    every level vanish (the approximation of a cubic is a cubic on the half
+    grid, and db4 has four vanishing moments)."""
+    n, levels = 256, 4
+    x = (np.arange(n) / n - 0.3) ** 3 + 0.2 * (np.arange(n) / n)
+    out = wavelet.forward(x, levels)
+    L = n
+    for lev in range(levels):
+        half = L // 2
+        d = out[half:L]
+        # outputs whose 8-tap window wraps, or reaches an input the wrap has
+        # already touched: the last 3, 5, 6, 6 of levels 1-4; 7 are skipped
+        keep = half - 7
+        assert keep > 8 and np.max(np.abs(d[:keep])) < 1e-12, lev
+        L = half
+
+
+def _dense_level(n, h):
+    """One periodised analysis level as an n x n matrix, rows a[k] then d[k]."""
+    g = wavelet.highpass(h)
+    A = np.zeros((n, n))
+    for k in range(n // 2):
+        for t in range(len(h)):
+            A[k, (2 * k + t) % n] += h[t]
+            A[n // 2 + k, (2 * k + t) % n] += g[t]
+    return A
+
+
+@pytest.mark.parametrize("shape,levels", [((32,), 3), ((16, 8), 2), ((8, 8, 16), 2), ((16, 16), 3)])
+def test_wavelet_multilevel_equals_dense_pyramid(shape, levels):
+    """The multi-level transform built independently as a product of dense
+    matrices: level l acts as the Kronecker product of the one-level matrices
+    on the approximation block of level l - 1 (leading n/2^l entries of every
+    axis) and as the identity on everything else."""
+    h = wavelet.db4_filter()
+    n = int(np.prod(shape))
+    idx = np.arange(n).reshape(shape)
+    Wt = np.eye(n)
+    for lev in range(levels):
+        sub = tuple(s >> lev for s in shape)
+        K = np.ones((1, 1))
+        for s in sub:
+            K = np.kron(K, _dense_level(s, h))
+        sel = idx[tuple(slice(0, s) for s in sub)].ravel()
+        Ml = np.eye(n)
+        Ml[np.ix_(sel, sel)] = K
+        Wt = Ml @ Wt
+    x = np.random.default_rng(3).standard_normal(shape) + 1j * np.random.default_rng(4).standard_normal(shape)
+    np.testing.assert_allclose(wavelet.forward(x, levels).ravel(), Wt @ x.ravel(), atol=1e-12)
+    np.testing.assert_allclose(wavelet.inverse(x, levels).ravel(), Wt.T @ x.ravel(), atol=1e-12)
+
+
+def test_wavelet_level_recursion():
+    """Level l equals the one-level transform of the level l - 1
+    approximation block, with the detail bands of earlier levels untouched."""
+    rng = np.random.default_rng(5)
+    shape = (32, 16, 16)
+    x = rng.standard_normal(shape)
+    for levels in (2, 3, 4):
+        full = wavelet.forward(x, levels)
+        prev = wavelet.forward(x, levels - 1)
+        blk = tuple(slice(0, s >> (levels - 1)) for s in shape)
+        want = prev.copy()
+        want[blk] = wavelet.forward(prev[blk], 1)
+        np.testing.assert_allclose(full, want, atol=1e-13)
+
+
 def test_soft_threshold_cases():
     v = np.array([0.0, 3 + 4j, 0.5j, -2.0])
     out = wavelet.soft(v, 1.0)
@@ -164,13 +255,20 @@ def test_power_method_matches_eigvalsh():
     assert abs(lam_i - np.linalg.norm(A, 2) ** 2) < 1e-10 * lam_i
 
 
-def test_schedule_recursion():
-    s, t, th = pdhg.schedule(4.0, 0.25, 5)
-    assert s[0] == 1.0 and t[0] == 0.25
-    for i in range(4):
-        assert th[i] == 1.0 / (1.0 + 2.0 * s[i] * 0.25)
-        assert s[i + 1] == th[i] * s[i] and t[i + 1] == t[i] / th[i]
-    np.testing.assert_allclose(s * t, 0.25)
+def test_schedule_closed_form():
+    """The accelerated schedule (theta_k = 1/(1 + 2 sigma_k gamma), sigma_{k+1}
+    = theta_k sigma_k, tau_{k+1} = tau_k / theta_k, gamma = min p) solved in
+    closed form: 1/sigma_{k+1} = 1/sigma_k + 2 gamma, so sigma_k =
+    sigma_0 / (1 + 2 k gamma sigma_0), tau_k = tau_0 (1 + 2 k gamma sigma_0)
+    and sigma_k tau_k stays sigma_0 tau_0 = 1 / lambda_max."""
+    lam_max, gam, K = 4.0, 0.25, 7
+    s, t, th = pdhg.schedule(lam_max, gam, K)
+    k = np.arange(len(s))
+    np.testing.assert_allclose(s, 1.0 / (1.0 + 2.0 * k * gam), rtol=1e-14)
+    np.testing.assert_allclose(t, (1.0 + 2.0 * k * gam) / lam_max, rtol=1e-14)
+    kk = np.arange(len(th))
+    np.testing.assert_allclose(th, (1.0 + 2.0 * kk * gam) / (1.0 + 2.0 * (kk + 1) * gam), rtol=1e-14)
+    np.testing.assert_allclose(s * t, 1.0 / lam_max, rtol=1e-14)
 
 
 def test_pdhg_l2_converges_to_cg_and_gap_closes():
