@@ -83,6 +83,7 @@ typedef struct {
     int64_t workspace_bytes;/* device bytes owned by the plan                 */
     int spread_bin_size[3]; /* spreading tiles                                */
     int64_t nspread_tiles;  /* number of spreading tiles                      */
+    int max_chunk;          /* spreading split size in use (kp_tuning)        */
 } kp_plan_info;
 
 /* PDHG options (host struct). */

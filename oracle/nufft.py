@@ -41,6 +41,7 @@ against its defining properties (tests/test_oracle_operators.py).
 """
 from __future__ import annotations
 
+import copy
 import itertools
 import math
 
@@ -165,6 +166,13 @@ class Nufft:
         self.pos = [(np.arange(n) - n // 2) % self.G[a] for a, n in enumerate(self.shape)]
         # taps: flat grid index and weight for every (sample, tap)
         self._taps = self._make_taps()
+
+    def with_maps(self, maps):
+        """The same operator (trajectory, grid, taps) with other coil maps."""
+        other = copy.copy(self)
+        other.maps = None if maps is None else np.asarray(maps, dtype=np.complex128)
+        other.C = 1 if maps is None else other.maps.shape[0]
+        return other
 
     def _make_taps(self):
         taps = []

@@ -39,6 +39,18 @@ def _dev(t, dtype, name):
     return t.contiguous()
 
 
+def _out(t, dtype, n, name):
+    """An output buffer the library writes through its pointer: a contiguous
+    device tensor of the right dtype and size, used as given (never a copy)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return _numel(t, n, name)
+
+
 def _numel(t, n, name):
     """Refuse a buffer whose size differs from what the library will read or
     write through its pointer (the C-ABI takes bare pointers)."""
@@ -82,6 +94,7 @@ class Plan:
             "nbins": inf.nbins, "ntouch": inf.ntouch, "nwork": inf.nwork,
             "heavy_tiles": inf.heavy_tiles, "workspace_bytes": inf.workspace_bytes,
             "spread_bin_size": tuple(inf.spread_bin_size[:d]), "nspread_tiles": inf.nspread_tiles,
+            "max_chunk": inf.max_chunk,
         }
 
     def sort(self):
@@ -149,7 +162,7 @@ def nufft_forward(plan: Plan, x, out=None):
     x = _numel(_dev(x, torch.complex64, "x"), _nimg(plan.shape), "x")
     if out is None:
         out = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device)
-    _numel(out, plan.ncoils * plan.nsamples, "out")
+    _out(out, torch.complex64, plan.ncoils * plan.nsamples, "out")
     _lib.check(_lib.load().nufft_forward(plan.handle, _ptr(x), _ptr(out), _stream()))
     return out
 
@@ -158,7 +171,7 @@ def nufft_adjoint(plan: Plan, y, out=None):
     y = _numel(_dev(y, torch.complex64, "y"), plan.ncoils * plan.nsamples, "y")
     if out is None:
         out = torch.empty(plan.shape, dtype=torch.complex64, device=plan.device)
-    _numel(out, _nimg(plan.shape), "out")
+    _out(out, torch.complex64, _nimg(plan.shape), "out")
     _lib.check(_lib.load().nufft_adjoint(plan.handle, _ptr(y), _ptr(out), _stream()))
     return out
 
@@ -340,7 +353,7 @@ def nufft_batch_info(batch: Batch, slice_index: int) -> dict:
     return {
         "shape": tuple(inf.shape[:d]), "grid": tuple(inf.grid[:d]), "bin_size": tuple(inf.bin_size[:d]),
         "nwork": inf.nwork, "heavy_tiles": inf.heavy_tiles, "fast": bool(fast.value),
-        "spread_bin_size": tuple(inf.spread_bin_size[:d]),
+        "spread_bin_size": tuple(inf.spread_bin_size[:d]), "max_chunk": inf.max_chunk,
     }
 
 

@@ -60,6 +60,7 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("spread_bin_size", ctypes.c_int * 3),
         ("nspread_tiles", ctypes.c_int64),
+        ("max_chunk", ctypes.c_int),
     ]
 
 

@@ -204,6 +204,7 @@ struct Plan {
     int64_t ntouch = 0;
     int64_t nwork = 0;
     int64_t heavy_tiles = 0;
+    int max_chunk = 0;            // spreading split size in use
     bool has_maps = false;
     hipStream_t stream = nullptr;
     int lds_max = 65536;

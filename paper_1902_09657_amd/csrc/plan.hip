@@ -720,6 +720,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
         max_chunk = 1024;
         while (max_chunk > kSpreadChunk && entries < (int64_t)4096 * max_chunk) max_chunk /= 2;
     }
+    P->max_chunk = max_chunk;
     std::vector<int4> heavy_items, light_items;
     std::vector<int4> heavy;  // (tile, first slot, slots, 0)
     int nslots = 0;
@@ -1219,6 +1220,7 @@ int nufft_plan_info(kp_plan_t plan, kp_plan_info* info) {
         info->ntouch = P.ntouch;
         info->nwork = P.nwork;
         info->heavy_tiles = P.heavy_tiles;
+        info->max_chunk = P.max_chunk;
         info->workspace_bytes = P.bytes;
     });
 }

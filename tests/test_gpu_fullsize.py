@@ -5,9 +5,13 @@
   workload also with the TV regulariser and, for l2, through its dual (10
   MC-preconditioned CG iterations).
 * 3D UTE 160^3, 8 coils, 2.56 M samples/coil (the timed workload, same plan as
-  the benchmark): the full forward and adjoint against the oracle, the adjoint
-  identity, and the first two PDHG iterations against the oracle (P = I and a
-  fixed lambda_max keep the oracle's cost to four NUFFTs per iteration).
+  the benchmark): the canonical coordinates, sort and touch lists bit for bit;
+  the full forward and adjoint against the oracle, the adjoint identity, and
+  the first two PDHG iterations against the oracle (P = I and a fixed
+  lambda_max keep the oracle's cost to four NUFFTs per iteration).  With two
+  of the eight coils on the full image and trajectory: the MC preconditioner
+  built at 2N, lambda_max with that p, and two l1-db4 iterations with that p
+  and the library's own power method.
 * Slices of the 64-slice batched workload, solved as one batch, against the
   oracle slice by slice.
 * The differentiable workload's slice size (256^2, 12 coils, 24 x 2048 spiral):
@@ -171,6 +175,73 @@ def test_3d_ute_adjoint_identity(ute):
     assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
 
 
+def test_3d_ute_sort_bit_exact(ute):
+    """The timed plan's canonical coordinates, sort and spreading touch lists
+    at full size (2.56 M samples, 8.4 M touch entries), bit for bit."""
+    kp, cfg, x, maps, k, w, op, plan = ute
+    info = plan.info()
+    G = onufft.grid_shape(cfg.shape, cfg.alpha)
+    assert tuple(info["grid"]) == G
+    print("3D UTE sort", info["bin_size"], info["spread_bin_size"], flush=True)
+    g_or = onufft.canonical_coords(k, G)
+    assert np.array_equal(plan.grid_coords().cpu().numpy().view(np.uint32), g_or.view(np.uint32))
+    perm_o, off_o = onufft.sort_by_bin(g_or, G, info["bin_size"])
+    perm, boff, toff, touch = [t.cpu().numpy() for t in plan.sort()]
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(boff, off_o)
+    toff_o, touch_o = onufft.tile_touch_lists(g_or[perm_o], G, info["spread_bin_size"], cfg.width)
+    assert np.array_equal(toff, toff_o)
+    assert np.array_equal(touch, touch_o)
+
+
+@pytest.fixture(scope="module")
+def ute2(ute):
+    """Two of the eight coils of the timed workload on the full 160^3 image and
+    trajectory, with the oracle's multi-channel preconditioner (built at 2N:
+    320^3 lags, 400^3 grid) and its power-method lambda_max (3 iterations:
+    the oracle needs about 14 s per NUFFT pair at this size)."""
+    kp, cfg, x, maps, k, w, op, plan = ute
+    m2 = maps[:2]
+    op2 = op.with_maps(m2)
+    plan2 = _plan(kp, k, cfg.shape, m2, cfg.alpha, cfg.width)
+    print("3D UTE two coils: oracle MC preconditioner at 2N", flush=True)
+    p_o = oprecond.efficient_nufft(m2, k, cfg.shape, cfg.alpha, cfg.width)
+    print("3D UTE two coils: oracle lambda_max", flush=True)
+    lmax_o = opdhg.power_method(op2.forward, op2.adjoint, p_o, cfg.shape, 3)
+    yield kp, cfg, x, m2, k, w[:2], op2, plan2, p_o, lmax_o
+    plan2.close()
+
+
+def test_3d_ute_mc_precond_full(ute2):
+    kp, cfg, x, m2, k, w, op2, plan2, p_o, lmax_o = ute2
+    p_g = kp.precond_build(plan2, kp.KP_PRECOND_MC).cpu().numpy()
+    r = rel(p_g, p_o)
+    print("3D UTE MC precond rel", r, flush=True)
+    assert np.all(p_g > 0)
+    assert r < 1e-4
+
+
+def test_3d_ute_lambda_max_mc(ute2):
+    kp, cfg, x, m2, k, w, op2, plan2, p_o, lmax_o = ute2
+    lg = float(kp.pdhg_lambda_max(plan2, dev(p_o, torch.float32), 3).item())
+    print("3D UTE lambda_max", lg, lmax_o, flush=True)
+    assert abs(lg - lmax_o) <= 1e-5 * lmax_o
+
+
+def test_3d_ute_pdhg_mc_power_method(ute2):
+    """Two l1-db4 PDHG iterations with the oracle's MC p; the library runs its
+    own power method inside pdhg_solve (lambda_max <= 0), the oracle uses its
+    own estimate (equal within 1e-5 by the test above)."""
+    kp, cfg, x, m2, k, w, op2, plan2, p_o, lmax_o = ute2
+    y = op2.forward(x) + w
+    xo, uo, _ = opdhg.pdhg(op2.forward, op2.adjoint, y, p_o, cfg.shape, "l1wav", cfg.lam, 2, lmax=lmax_o, levels=4)
+    xg, ug = kp.pdhg_solve(plan2, dev(y, torch.complex64), dev(p_o, torch.float32), reg="l1wav", lam=cfg.lam,
+                           iters=2, wavelet_levels=4, lambda_max=0.0, power_iters=3, want_u=True)
+    rx, ru = rel(xg.cpu().numpy(), xo), rel(ug.cpu().numpy(), uo)
+    print("3D UTE MC PDHG rel x", rx, "u", ru, flush=True)
+    assert rx < 1e-4 and ru < 1e-4
+
+
 def test_3d_ute_pdhg_first_iterations(ute):
     kp, cfg, x, maps, k, w, op, plan = ute
     print("3D UTE two PDHG iterations", flush=True)
@@ -217,17 +288,19 @@ def test_batched_workload_slices():
 
 
 def test_batched_workload_all_64_slices():
-    """The whole 64-slice batch, one pdhg_solve_batch as the benchmark times it:
-    every slice equals its plain per-slice solve (itself held to the oracle),
-    and two sampled slices (one per grid length 160 and 240) equal the FP64
-    oracle.  The sampled slices take their data, preconditioner and lambda_max
-    from the oracle side only; every slice uses the single-channel
-    preconditioner, since one batch call takes one preconditioner kind."""
+    """The whole 64-slice batch as the benchmark times it: phantom data, the
+    multi-channel preconditioner and each slice's own power-method lambda_max
+    (30 iterations), one pdhg_solve_batch.  Every slice equals the plain
+    per-slice solve on a plan with the batch's tiles within 1e-6; two
+    sampled slices (one of size 128, one of size 192) take their data, MC
+    preconditioner and lambda_max from the oracle side only and equal the
+    FP64 oracle within 1e-4 (their GPU lambda_max within 1e-5 of the
+    oracle's)."""
     kp = _kp()
     C, K, lam = 12, 20, 1e-3
     sl = synth.slice_config4(64, seed=4, ncoils=C)
     pick = [[i for i, (s, _) in enumerate(sl) if s[0] == n][0] for n in (128, 192)]
-    coords, maps_l, ys, ps, lms, plans, ops = [], [], [], [], [], [], {}
+    coords, maps_l, ys, ps, lms, ops = [], [], [], [], [], {}
     print("batched 64 slices, oracle-sampled", pick, flush=True)
     for i, (shape, k) in enumerate(sl):
         rp, rm, _, rn = synth.streams(4000 + i)
@@ -238,33 +311,42 @@ def test_batched_workload_all_64_slices():
         if i in pick:
             op = onufft.Nufft(k, shape, m, 1.25, 4)
             y = op.forward(x) + synth.noise((C, k.shape[0]), 1e-3, rn)
-            p = oprecond.efficient_nufft(None, k, shape, 1.25, 4)[0]
-            ops[i] = (op, y, p)
+            p = oprecond.efficient_nufft(m, k, shape, 1.25, 4)
+            lm = opdhg.power_method(op.forward, op.adjoint, p, shape, 30)
+            lg = float(kp.pdhg_lambda_max(pl, dev(p, torch.float32), 30).item())
+            print("slice", i, shape, "lambda_max gpu", lg, "oracle", lm, flush=True)
+            assert abs(lg - lm) <= 1e-5 * lm
+            ops[i] = (op, y, p, lm)
             yt, pt = dev(y, torch.complex64), dev(p, torch.float32)
         else:
-            yt = dev(synth.noise((C, k.shape[0]), 1.0, rn), torch.complex64)
-            pt = kp.precond_build(pl, kp.KP_PRECOND_SC)   # one kind per batch
+            yt = kp.nufft_forward(pl, dev(x, torch.complex64)) + dev(synth.noise((C, k.shape[0]), 1e-3, rn),
+                                                                     torch.complex64)
+            pt = kp.precond_build(pl, kp.KP_PRECOND_MC)
+            lm = float(kp.pdhg_lambda_max(pl, pt, 30).item())
+        pl.close()
         coords.append(kt)
         maps_l.append(mt)
         ys.append(yt)
         ps.append(pt)
-        lms.append(1.5)
-        plans.append(pl)
+        lms.append(lm)
     b = kp.nufft_plan_batch(coords, [s for s, _ in sl], maps_l, oversamp=1.25, kb_width=4, tune=True)
     assert all(kp.nufft_batch_info(b, j)["fast"] for j in range(len(sl)))
     with pytest.raises(ValueError):   # mixed preconditioner kinds are refused
-        kp.pdhg_solve_batch(b, ys, ps[:1] + [p.expand(C, -1).contiguous() for p in ps[1:]], lam=lam, iters=K, lambda_max=lms)
+        kp.pdhg_solve_batch(b, ys, ps[:1] + [p[0].contiguous() for p in ps[1:]], lam=lam, iters=K, lambda_max=lms)
     xb = kp.pdhg_solve_batch(b, ys, ps, lam=lam, iters=K, lambda_max=lms)
     worst = 0.0
-    for i, pl in enumerate(plans):
+    for i, (shape, k) in enumerate(sl):
+        inf = kp.nufft_batch_info(b, i)
+        pl = kp.nufft_plan(coords[i], shape, maps_l[i], oversamp=1.25, kb_width=4, bin_size=inf["bin_size"],
+                           max_chunk=inf["max_chunk"], spread_bin_size=inf["spread_bin_size"])
         xp = kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=lam, iters=K, lambda_max=lms[i])
         worst = max(worst, rel(xb[i].cpu().numpy(), xp.cpu().numpy()))
         pl.close()
-    print("batch vs plain, worst rel", worst, flush=True)
-    assert worst < 1e-5
+    print("batch vs plain (same tiles), worst rel", worst, flush=True)
+    assert worst < 1e-6
     for i in pick:
-        op, y, p = ops[i]
-        xo, _, _ = opdhg.pdhg(op.forward, op.adjoint, y, p, sl[i][0], "l2", lam, K, lmax=1.5)
+        op, y, p, lm = ops[i]
+        xo, _, _ = opdhg.pdhg(op.forward, op.adjoint, y, p, sl[i][0], "l2", lam, K, lmax=lm)
         r = rel(xb[i].cpu().numpy(), xo)
         print("slice", i, sl[i][0], "rel vs oracle", r, flush=True)
         assert r < 1e-4

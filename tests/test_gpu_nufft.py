@@ -88,6 +88,9 @@ def test_grid_coords_and_sort_bit_exact(shape, C, M, alpha, W):
     plan.close()
 
 
+NSPECIAL = 8   # synth.random_coords puts its special points first
+
+
 @pytest.mark.parametrize("shape,C,M,alpha,W", CASES)
 def test_forward_adjoint_parity(shape, C, M, alpha, W):
     kp = _kp()
@@ -96,9 +99,24 @@ def test_forward_adjoint_parity(shape, C, M, alpha, W):
     op = onufft.Nufft(k, shape, maps, alpha, W)
     plan = _plan(kp, k, shape, maps, alpha, W)
     yg = kp.nufft_forward(plan, dev(x, torch.complex64)).cpu().numpy()
-    assert rel(yg, op.forward(x)) < 1e-4
+    yo = op.forward(x)
+    assert rel(yg, yo) < 1e-4
+    # the special samples one by one (k = 0, -pi, just below pi, exactly on
+    # grid lines), where an edge tap of the wrong weight would be diluted in
+    # the global figure: each sample's coil vector within 1e-4 of the oracle's
+    for i in range(NSPECIAL):
+        e = np.linalg.norm(yg[:, i] - yo[:, i]) / max(np.linalg.norm(yo[:, i]), 1e-2 * np.sqrt(np.mean(np.abs(yo) ** 2)))
+        assert e < 1e-4, (i, k[i], e)
     xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
     assert rel(xg, op.adjoint(y)) < 1e-4
+    # adjoint of each special sample alone (a unit value in coil 0): its
+    # spreading weights decide the whole image
+    for i in range(NSPECIAL):
+        yi = np.zeros((C, M), np.complex128)
+        yi[0, i] = 1.0
+        xi = kp.nufft_adjoint(plan, dev(yi, torch.complex64)).cpu().numpy()
+        e = rel(xi, op.adjoint(yi))
+        assert e < 1e-4, (i, k[i], e)
     plan.close()
 
 
