@@ -131,6 +131,19 @@ int nufft_plan(kp_plan_t* out, int ndim, const int64_t* shape, int64_t ncoils,
  * overwritten. */
 int nufft_forward(kp_plan_t plan, const void* x, void* y, void* stream);
 
+/* nufft_forward for callers that cannot allocate device memory where they
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same operation and arguments as nufft_forward, but
+ * the two FFT ping-pong grids come from a static per-device array of
+ * 2 x 16 MiB that the library holds until the process ends, not from the
+ * plan's workspaces.  Allocates nothing.  A plan whose grid needs more than
+ * 16 MiB per buffer (G_0..G_{d-1} x C x 8 bytes; e.g. 2D 400^2 grids up to
+ * 13 coils) is refused with KP_ERR_UNSUPPORTED before any launch.  Every
+ * call on one device shares that device's array: calls that overlap in time
+ * on one device (different streams or threads) race and must not be issued;
+ * calls ordered on one stream are safe. */
+int nufft_forward_noalloc(kp_plan_t plan, const void* x, void* y, void* stream);
+
 /* x = A^H y: Kaiser-Bessel spreading accumulated per tile in LDS, inverse
  * oversampled FFT, crop, deapodisation, conj(s_c) and coil sum.
  * y: c64 [C][M] caller order; x: c64 [N], overwritten. */

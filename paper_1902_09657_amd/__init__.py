@@ -16,7 +16,7 @@ from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVE
                    KpError, PdhgOpts, PlanInfo, Tuning)
 
 __all__ = [
-    "Plan", "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
+    "Plan", "nufft_plan", "nufft_forward", "nufft_forward_noalloc", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
     "pdhg_solve", "l2_dual_cg", "nufft_destroy", "nufft_autotune", "Batch", "nufft_plan_batch", "nufft_batch_info",
     "pdhg_solve_batch", "nufft_batch_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
     "KP_REG_L2", "KP_REG_L1_WAVELET", "KP_REG_TV",
@@ -164,6 +164,15 @@ def nufft_forward(plan: Plan, x, out=None):
         out = torch.empty((plan.ncoils, plan.nsamples), dtype=torch.complex64, device=plan.device)
     _out(out, torch.complex64, plan.ncoils * plan.nsamples, "out")
     _lib.check(_lib.load().nufft_forward(plan.handle, _ptr(x), _ptr(out), _stream()))
+    return out
+
+
+def nufft_forward_noalloc(plan: Plan, x, out):
+    """nufft_forward with the FFT grids in the library's static per-device
+    array: no device allocation in the library, `out` supplied by the caller."""
+    x = _numel(_dev(x, torch.complex64, "x"), _nimg(plan.shape), "x")
+    _out(out, torch.complex64, plan.ncoils * plan.nsamples, "out")
+    _lib.check(_lib.load().nufft_forward_noalloc(plan.handle, _ptr(x), _ptr(out), _stream()))
     return out
 
 

@@ -23,7 +23,7 @@ KP_REG_L2, KP_REG_L1_WAVELET, KP_REG_TV = 0, 1, 2
 
 # every symbol the header declares
 EXPORTS = [
-    "nufft_plan", "nufft_forward", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
+    "nufft_plan", "nufft_forward", "nufft_forward_noalloc", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
     "pdhg_solve", "pdhg_unrolled_ckpt_bytes", "pdhg_unrolled_forward", "pdhg_unrolled_backward",
     "nufft_destroy", "nufft_plan_info", "nufft_plan_sort", "nufft_plan_grid_coords",
     "kp_db4_filter", "nufft_plan_validate", "kp_last_error", "nufft_stage",
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "nufft_plan": (i32, [P(vp), i32, P(i64), i64, i64, vp, vp, f32, i32, P(Tuning), vp]),
         "nufft_forward": (i32, [vp, vp, vp, vp]),
+        "nufft_forward_noalloc": (i32, [vp, vp, vp, vp]),
         "nufft_adjoint": (i32, [vp, vp, vp, vp]),
         "precond_build": (i32, [vp, i32, vp, vp]),
         "pdhg_lambda_max": (i32, [vp, vp, i32, i32, vp, vp]),

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkpdhg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["plan.hip", "fft.hip", "grid.hip", "solver.hip", "precond.hip", "unrolled.hip", "batch.hip"]
+SOURCES = ["plan.hip", "fft.hip", "grid.hip", "solver.hip", "precond.hip", "unrolled.hip", "batch.hip", "noalloc.hip"]
 
 
 def hipcc() -> str:

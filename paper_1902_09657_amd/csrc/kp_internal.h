@@ -250,6 +250,7 @@ struct FwdOpts {
     const float* xscale = nullptr;   // device scalar multiplying x
     bool channel = false;            // x is [N][C] (no maps)
     int C = -1;                      // channels (<= plan C), -1 = plan C
+    float2* bufs[2] = {nullptr, nullptr};  // ping-pong grids instead of the plan's bufA / bufB
 };
 // Pre-pass + FFT passes: image -> grid (result in plan bufA or bufB; returned)
 float2* forward_to_grid(Plan& P, const float2* x, const FwdOpts& o, hipStream_t s);

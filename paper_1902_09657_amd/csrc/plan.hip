@@ -929,7 +929,7 @@ static void set_xrange(const Plan& P, int C, int mode, FftPass& fp) {
 std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o) {
     const int C = o.C < 0 ? (int)P.C : o.C;
     const int d = P.d;
-    float2* bufs[2] = {P.bufA.as<float2>(), P.bufB.as<float2>()};
+    float2* bufs[2] = {o.bufs[0] ? o.bufs[0] : P.bufA.as<float2>(), o.bufs[1] ? o.bufs[1] : P.bufB.as<float2>()};
     int which = 0;
     const float2* prev = nullptr;
     std::vector<FftPass> out;
