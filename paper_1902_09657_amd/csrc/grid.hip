@@ -368,35 +368,43 @@ __global__ void __launch_bounds__(256) k_interp_tile(InterpArgs a, const int4* _
     }
 }
 
-// 3D, width 4, four coils per block: the lanes of one 16-lane row serve one
-// sample (4 coils x the 4 taps along z), so for each of the 16 (x, y) taps a
-// row reads one contiguous 128-byte run of the halo; rows of one halo line
-// are padded to H2P cells (H2P = 4 mod 8) so that the two rows of a 32-lane
-// LDS pass never meet in a bank when they read neighbouring halo lines.  The
-// weights of up to 256 samples are computed once per batch into an LDS table;
-// the 4 z-tap partial sums of a coil are added by a two-step DPP row shift.
+// 3D, width 4, CG coils per block (CG = 4 or 2): the lanes of one group of
+// 4 CG lanes serve one sample (CG coils x the 4 taps along z), so for each of
+// the 16 (x, y) taps a group reads one contiguous run of 4 CG complex values
+// of the halo; rows of one halo line are padded to H2P cells.  The weights of
+// up to kTlBatch samples are computed once per batch into an LDS table, whose
+// rows also take the interpolated values of their sample (each row is read
+// only by its own sample's lanes before they write it); the 4 z-tap partial
+// sums of a coil are added by a two-step DPP row shift.
 __device__ __forceinline__ float dpp_row_shr4(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_row_shr8(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
 }
+__device__ __forceinline__ float dpp_row_shr2(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+}
 
 constexpr int kTlBatch = 256;  // samples whose weights sit in LDS at a time
 constexpr int kTlStage = 12;   // halo loads per thread held in registers
+constexpr int kTlCG = 4;       // coils per block of the tap-lane interpolation
 
 __host__ __device__ inline int tl_h2p(int H2) { return H2 + ((12 - H2 % 8) % 8); }
 
 // TB0..TB2: the tile shape as compile-time constants (0: taken from the
 // arguments).  With constants every halo index is a multiply-shift and the
 // 16 tap offsets fold into the LDS instructions' immediate offsets.
-template <int TB0, int TB1, int TB2>
+template <int TB0, int TB1, int TB2, int CG>
 __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
+    static_assert(CG == 2 || CG == 4, "coil groups of 2 or 4");
+    constexpr int NP = CG / 2;          // float4 (two coils) per cell
+    constexpr int SPW = 64 / (4 * CG);  // samples per wave
     extern __shared__ float4 tl_smem[];
-    const int ncg = a.C / 4;
+    const int ncg = a.C / CG;
     // The coil groups of one piece are launched 8 blocks apart (blocks are
-    // dealt to the 8 XCDs in turn, so they tend to share an L2 and the second
-    // half of every 64-byte grid cell is found there).
+    // dealt to the 8 XCDs in turn, so they tend to share an L2 and the rest
+    // of every grid cell's coil vector is found there).
     int item, cg;
     {
         const int b = blockIdx.x, nitems = gridDim.x / ncg;
@@ -422,25 +430,25 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
     const int H0 = (TB0 ? TB0 : a.B[0]) + 3, H1 = (TB1 ? TB1 : a.B[1]) + 3, H2 = (TB2 ? TB2 : a.B[2]) + 3;
     const int H2P = tl_h2p(H2);
     const int hcells = H0 * H1 * H2;
-    float2* halo = reinterpret_cast<float2*>(tl_smem);                    // [H0][H1][H2P][4]
-    float* tab = reinterpret_cast<float*>(halo + (size_t)H0 * H1 * H2P * 4);  // [kTlBatch][16]
-    float2* obuf = reinterpret_cast<float2*>(tab + kTlBatch * 16);               // [kTlBatch][4]
+    float2* halo = reinterpret_cast<float2*>(tl_smem);                        // [H0][H1][H2P][CG]
+    float* tab = reinterpret_cast<float*>(halo + (size_t)H0 * H1 * H2P * CG);  // [kTlBatch][16]
     const int C = a.C;
     const int tid = threadIdx.x;
 
     // ---- halo loads into registers (two coils per float4)
-    // 8^3 tiles (11^3 halo): thread t < 242 takes float4 t % 22 of the z-rows
-    // (h0, h1 = t / 22) for h0 = 0..10, so only h0 varies between its loads;
-    // other shapes: the halo's float4s dealt out in order.
+    // 8^3 tiles (11^3 halo): thread t < 11 * 11 NP takes float4 t % (11 NP)
+    // of the z-rows (h0, h1 = t / (11 NP)) for h0 = 0..10, so only h0 varies
+    // between its loads; other shapes: the halo's float4s dealt out in order.
     constexpr bool ROWS = TB0 == 8 && TB1 == 8 && TB2 == 8;
+    constexpr int RW = 11 * NP;  // float4 per z-row of the 11^3 halo
     float4 hv[kTlStage];
     if (ROWS) {
-        if (tid < 242) {
-            const int h1 = tid / 22, pos = tid % 22, h2 = pos >> 1, part = pos & 1;
+        if (tid < 11 * RW) {
+            const int h1 = tid / RW, pos = tid % RW, h2 = pos / NP, part = pos % NP;
             int j1 = org[1] - 1 + h1, j2 = org[2] - 1 + h2;
             j1 = j1 < 0 ? j1 + a.G[1] : (j1 >= a.G[1] ? j1 - a.G[1] : j1);
             j2 = j2 < 0 ? j2 + a.G[2] : (j2 >= a.G[2] ? j2 - a.G[2] : j2);
-            const float2* rowp = a.grid + ((int64_t)j1 * a.G[2] + j2) * C + cg * 4 + part * 2;
+            const float2* rowp = a.grid + ((int64_t)j1 * a.G[2] + j2) * C + cg * CG + part * 2;
             const int64_t plane = (int64_t)a.G[1] * a.G[2] * C;
 #pragma unroll
             for (int r = 0; r < 11; ++r) {
@@ -453,25 +461,25 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
 #pragma unroll
         for (int r = 0; r < kTlStage; ++r) {
             const int i = tid + r * 256;
-            if (i < hcells * 2) {
-                const int cell = i >> 1, part = i & 1;
+            if (i < hcells * NP) {
+                const int cell = i / NP, part = i % NP;
                 const int h2 = cell % H2, h01 = cell / H2, h1 = h01 % H1, h0 = h01 / H1;
                 int j0 = org[0] - 1 + h0, j1 = org[1] - 1 + h1, j2 = org[2] - 1 + h2;
                 j0 = j0 < 0 ? j0 + a.G[0] : (j0 >= a.G[0] ? j0 - a.G[0] : j0);
                 j1 = j1 < 0 ? j1 + a.G[1] : (j1 >= a.G[1] ? j1 - a.G[1] : j1);
                 j2 = j2 < 0 ? j2 + a.G[2] : (j2 >= a.G[2] ? j2 - a.G[2] : j2);
                 const int64_t gi = ((int64_t)j0 * a.G[1] + j1) * a.G[2] + j2;
-                hv[r] = *reinterpret_cast<const float4*>(a.grid + gi * C + cg * 4 + part * 2);
+                hv[r] = *reinterpret_cast<const float4*>(a.grid + gi * C + cg * CG + part * 2);
             }
         }
     }
 
     const int lane = tid & 63, wave = tid >> 6;
-    const int c = lane & 3, t2 = (lane >> 2) & 3, sub = lane >> 4;
+    const int c = lane % CG, t2 = (lane / CG) & 3, sub = lane / (4 * CG);
     // halo offsets (in float2) of the 16 (x, y) taps relative to a sample's base
     int toff[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) toff[t] = (((t >> 2) * H1 + (t & 3)) * H2P) * 4;
+    for (int t = 0; t < 16; ++t) toff[t] = (((t >> 2) * H1 + (t & 3)) * H2P) * CG;
     for (int b0 = 0; b0 < count; b0 += kTlBatch) {
         const int nbt = min(kTlBatch, count - b0);
         if (b0 > 0) __syncthreads();  // the previous batch is done with the table
@@ -494,12 +502,12 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
             row[3] = make_float4(__int_as_float((l[0] * H1 + l[1]) * H2P + l[2]), 0.f, 0.f, 0.f);
         }
         if (b0 == 0 && ROWS) {
-            if (tid < 242) {
-                const int h1 = tid / 22, pos = tid % 22;
-                float2* dst = halo + ((size_t)h1 * H2P + (pos >> 1)) * 4 + (pos & 1) * 2;
+            if (tid < 11 * RW) {
+                const int h1 = tid / RW, pos = tid % RW;
+                float2* dst = halo + ((size_t)h1 * H2P + pos / NP) * CG + (pos % NP) * 2;
 #pragma unroll
                 for (int r = 0; r < 11; ++r) {
-                    float2* d = dst + (size_t)r * H1 * H2P * 4;
+                    float2* d = dst + (size_t)r * H1 * H2P * CG;
                     d[0] = make_float2(hv[r].x, hv[r].y);
                     d[1] = make_float2(hv[r].z, hv[r].w);
                 }
@@ -508,107 +516,135 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
 #pragma unroll
             for (int r = 0; r < kTlStage; ++r) {
                 const int i = tid + r * 256;
-                if (i < hcells * 2) {
-                    const int cell = i >> 1, part = i & 1;
+                if (i < hcells * NP) {
+                    const int cell = i / NP, part = i % NP;
                     const int h2 = cell % H2, h01 = cell / H2;
-                    float2* dst = halo + ((size_t)h01 * H2P + h2) * 4 + part * 2;
+                    float2* dst = halo + ((size_t)h01 * H2P + h2) * CG + part * 2;
                     dst[0] = make_float2(hv[r].x, hv[r].y);
                     dst[1] = make_float2(hv[r].z, hv[r].w);
                 }
             }
         }
         __syncthreads();
-        // ---- one sample per 16-lane row
-        for (int i = wave * 4 + sub; i < nbt; i += 16) {
-            const float* row = tab + i * 16;
+        // ---- one sample per group of 4 CG lanes
+        for (int i = wave * SPW + sub; i < nbt; i += 4 * SPW) {
+            float* row = tab + i * 16;
             const float4 w0 = *reinterpret_cast<const float4*>(row);
             const float4 w1 = *reinterpret_cast<const float4*>(row + 4);
             const float w2 = row[8 + t2];
             const int base = __float_as_int(row[12]);
             const float w0v[4] = {w0.x, w0.y, w0.z, w0.w};
             const float w1v[4] = {w1.x * w2, w1.y * w2, w1.z * w2, w1.w * w2};
-            const int hb = (base + t2) * 4 + c;
-            float2 hv[16];  // all 16 reads issued before the first use
+            const int hb = (base + t2) * CG + c;
+            float2 hvv[16];  // all 16 reads issued before the first use
 #pragma unroll
-            for (int t = 0; t < 16; ++t) hv[t] = halo[hb + toff[t]];
+            for (int t = 0; t < 16; ++t) hvv[t] = halo[hb + toff[t]];
             // axis-1 taps first, then the axis-0 weight once per t0
             float ax = 0.f, ay = 0.f;
 #pragma unroll
             for (int t0 = 0; t0 < 4; ++t0) {
-                float sx = w1v[0] * hv[t0 * 4].x, sy = w1v[0] * hv[t0 * 4].y;
+                float sx = w1v[0] * hvv[t0 * 4].x, sy = w1v[0] * hvv[t0 * 4].y;
 #pragma unroll
                 for (int t1 = 1; t1 < 4; ++t1) {
-                    sx = fmaf(w1v[t1], hv[t0 * 4 + t1].x, sx);
-                    sy = fmaf(w1v[t1], hv[t0 * 4 + t1].y, sy);
+                    sx = fmaf(w1v[t1], hvv[t0 * 4 + t1].x, sx);
+                    sy = fmaf(w1v[t1], hvv[t0 * 4 + t1].y, sy);
                 }
                 ax = fmaf(w0v[t0], sx, ax);
                 ay = fmaf(w0v[t0], sy, ay);
             }
-            ax += dpp_row_shr4(ax);
-            ay += dpp_row_shr4(ay);
-            ax += dpp_row_shr8(ax);
-            ay += dpp_row_shr8(ay);
-            if (t2 == 3) obuf[i * 4 + c] = make_float2(ax, ay);
+            if (CG == 4) {
+                ax += dpp_row_shr4(ax);
+                ay += dpp_row_shr4(ay);
+                ax += dpp_row_shr8(ax);
+                ay += dpp_row_shr8(ay);
+            } else {
+                ax += dpp_row_shr2(ax);
+                ay += dpp_row_shr2(ay);
+                ax += dpp_row_shr4(ax);
+                ay += dpp_row_shr4(ay);
+            }
+            // the row's reads above are done (their values fed the sums), so
+            // its first CG complex slots take the result
+            if (t2 == 3) reinterpret_cast<float2*>(row)[c] = make_float2(ax, ay);
         }
         __syncthreads();
-        // ---- output stage of the batch: one sample's 4 coils per thread
-        // (32 contiguous bytes of every [sample][coil] array, 16-byte accesses)
+        // ---- output stage of the batch: one sample's CG coils per thread
+        // (CG contiguous complex values of every [sample][coil] array,
+        // 16-byte accesses)
         for (int i = tid; i < nbt; i += 256) {
             const int64_t s = start + b0 + i;
-            const int64_t e = s * C + cg * 4;
-            const float4* ob = reinterpret_cast<const float4*>(obuf + i * 4);
-            const float4 v01 = ob[0], v23 = ob[1];
+            const int64_t e = s * C + cg * CG;
+            const float4* ob = reinterpret_cast<const float4*>(tab + i * 16);
+            float4 v[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) v[q] = ob[q];
             if (a.mode == IO_CALLER) {
                 const int64_t ps = a.perm[s];
-                const int64_t c0 = (int64_t)(cg * 4) * a.M + ps;
-                a.out[c0] = make_float2(v01.x, v01.y);
-                a.out[c0 + a.M] = make_float2(v01.z, v01.w);
-                a.out[c0 + 2 * a.M] = make_float2(v23.x, v23.y);
-                a.out[c0 + 3 * a.M] = make_float2(v23.z, v23.w);
+                const int64_t c0 = (int64_t)(cg * CG) * a.M + ps;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    a.out[c0 + (2 * q) * a.M] = make_float2(v[q].x, v[q].y);
+                    a.out[c0 + (2 * q + 1) * a.M] = make_float2(v[q].z, v[q].w);
+                }
                 continue;
             }
             float4* o4 = reinterpret_cast<float4*>(a.mode == IO_DUAL ? a.u + e : a.out + e);
             if (a.mode == IO_INTERNAL) {
-                o4[0] = v01;
-                o4[1] = v23;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) o4[q] = v[q];
                 continue;
             }
-            float4 pv = make_float4(1.f, 1.f, 1.f, 1.f);
+            float pv[CG];
+#pragma unroll
+            for (int q = 0; q < CG; ++q) pv[q] = 1.f;
             if (a.p) {
                 if (a.p_mc) {
-                    pv = *reinterpret_cast<const float4*>(a.p + e);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        const float2 pp = *reinterpret_cast<const float2*>(a.p + e + 2 * q);
+                        pv[2 * q] = pp.x;
+                        pv[2 * q + 1] = pp.y;
+                    }
                 } else {
-                    const float q = a.p[s];
-                    pv = make_float4(q, q, q, q);
+                    const float pq = a.p[s];
+#pragma unroll
+                    for (int q = 0; q < CG; ++q) pv[q] = pq;
                 }
             }
             if (a.mode == IO_PMUL) {
-                o4[0] = make_float4(pv.x * v01.x, pv.x * v01.y, pv.y * v01.z, pv.y * v01.w);
-                o4[1] = make_float4(pv.z * v23.x, pv.z * v23.y, pv.w * v23.z, pv.w * v23.w);
+#pragma unroll
+                for (int q = 0; q < NP; ++q)
+                    o4[q] = make_float4(pv[2 * q] * v[q].x, pv[2 * q] * v[q].y, pv[2 * q + 1] * v[q].z,
+                                        pv[2 * q + 1] * v[q].w);
                 continue;
             }
             // IO_DUAL: u <- (u + sigma p (v - y)) / (1 + sigma p)
             const float sg = *a.sigma;
             const float4* y4 = reinterpret_cast<const float4*>(a.y + e);
-            const float4 u01 = o4[0], u23 = o4[1], y01 = y4[0], y23 = y4[1];
-            const float sp0 = sg * pv.x, sp1 = sg * pv.y, sp2 = sg * pv.z, sp3 = sg * pv.w;
-            const float d0 = 1.f / (1.f + sp0), d1 = 1.f / (1.f + sp1);
-            const float d2 = 1.f / (1.f + sp2), d3 = 1.f / (1.f + sp3);
-            o4[0] = make_float4((u01.x + sp0 * (v01.x - y01.x)) * d0, (u01.y + sp0 * (v01.y - y01.y)) * d0,
-                                (u01.z + sp1 * (v01.z - y01.z)) * d1, (u01.w + sp1 * (v01.w - y01.w)) * d1);
-            o4[1] = make_float4((u23.x + sp2 * (v23.x - y23.x)) * d2, (u23.y + sp2 * (v23.y - y23.y)) * d2,
-                                (u23.z + sp3 * (v23.z - y23.z)) * d3, (u23.w + sp3 * (v23.w - y23.w)) * d3);
+            float4 uo[NP], yo[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                uo[q] = o4[q];
+                yo[q] = y4[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const float sp0 = sg * pv[2 * q], sp1 = sg * pv[2 * q + 1];
+                const float d0 = 1.f / (1.f + sp0), d1 = 1.f / (1.f + sp1);
+                o4[q] = make_float4((uo[q].x + sp0 * (v[q].x - yo[q].x)) * d0, (uo[q].y + sp0 * (v[q].y - yo[q].y)) * d0,
+                                    (uo[q].z + sp1 * (v[q].z - yo[q].z)) * d1, (uo[q].w + sp1 * (v[q].w - yo[q].w)) * d1);
+            }
         }
     }
 }
 
-size_t interp_tl3_lds_bytes(const int* B) {
+size_t interp_tl3_lds_bytes(const int* B, int CG = kTlCG) {
     const int H0 = B[0] + 3, H1 = B[1] + 3, H2P = tl_h2p(B[2] + 3);
-    return (size_t)H0 * H1 * H2P * 4 * sizeof(float2) + (size_t)kTlBatch * (16 * sizeof(float) + 4 * sizeof(float2));
+    return (size_t)H0 * H1 * H2P * CG * sizeof(float2) + (size_t)kTlBatch * 16 * sizeof(float);
 }
 
 bool interp_tl3_ok(int d, int W, const int* B, int C) {
-    return d == 3 && W == 4 && C % 4 == 0 && (B[0] + 3) * (B[1] + 3) * (B[2] + 3) * 2 <= kTlStage * 256 &&
+    return d == 3 && W == 4 && C % kTlCG == 0 && (B[0] + 3) * (B[1] + 3) * (B[2] + 3) * (kTlCG / 2) <= kTlStage * 256 &&
            interp_tl3_lds_bytes(B) <= 80 * 1024;
 }
 
@@ -644,19 +680,19 @@ void launch_interp_tiles(int d, int W, const InterpArgs& a, const int4* items, i
                          hipStream_t s) {
     if (a.M <= 0 || nitems <= 0) return;
     if (interp_tl3_ok(d, W, a.B, a.C)) {
-        const int64_t nb = nitems * (a.C / 4);
+        const int64_t nb = nitems * (a.C / kTlCG);
         if (nb > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "interpolation grid too large");
         const size_t lds = interp_tl3_lds_bytes(a.B);
         const bool b888 = a.B[0] == 8 && a.B[1] == 8 && a.B[2] == 8;
-        const void* fn = b888 ? (const void*)k_interp_tl3<8, 8, 8> : (const void*)k_interp_tl3<0, 0, 0>;
+        const void* fn = b888 ? (const void*)k_interp_tl3<8, 8, 8, kTlCG> : (const void*)k_interp_tl3<0, 0, 0, kTlCG>;
         if (lds > 65536) {
             (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             (void)hipGetLastError();
         }
         if (b888)
-            hipLaunchKernelGGL((k_interp_tl3<8, 8, 8>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+            hipLaunchKernelGGL((k_interp_tl3<8, 8, 8, kTlCG>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
         else
-            hipLaunchKernelGGL((k_interp_tl3<0, 0, 0>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+            hipLaunchKernelGGL((k_interp_tl3<0, 0, 0, kTlCG>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
         KP_LAUNCH_CHECK();
         return;
     }

@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
+#include <set>
 
 #include "kp_internal.h"
 
@@ -51,8 +53,36 @@ __global__ void k_perm_p_out(const float* q, float* p, const int32_t* perm, int6
     }
 }
 
+// One thread per sorted sample, all C coils: every load instruction of a
+// wave reads one coil row at 64 neighbouring sorted samples (runs of
+// consecutive caller indices along a trajectory), and each thread stores its
+// sample's C values as one contiguous run of 16-byte stores.
+template <int C>
+__global__ void k_perm_in_c(const float2* __restrict__ y, float2* __restrict__ k, const int32_t* __restrict__ perm,
+                            int64_t M) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    const int64_t ps = perm[s];
+    float2 v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = y[(int64_t)c * M + ps];
+    float4* dst = reinterpret_cast<float4*>(k + s * C);
+#pragma unroll
+    for (int q = 0; q < C / 2; ++q) dst[q] = make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
+}
+
 void permute_to_internal(const float2* y, float2* k, const int32_t* perm, int64_t M, int C, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_in, dim3(nblk(M * C)), dim3(256), 0, s, y, k, perm, M, C);
+    if (M <= 0) return;
+    if (C == 8)
+        hipLaunchKernelGGL(k_perm_in_c<8>, dim3(nblk(M)), dim3(256), 0, s, y, k, perm, M);
+    else if (C == 12)
+        hipLaunchKernelGGL(k_perm_in_c<12>, dim3(nblk(M)), dim3(256), 0, s, y, k, perm, M);
+    else if (C == 4)
+        hipLaunchKernelGGL(k_perm_in_c<4>, dim3(nblk(M)), dim3(256), 0, s, y, k, perm, M);
+    else if (C == 2)
+        hipLaunchKernelGGL(k_perm_in_c<2>, dim3(nblk(M)), dim3(256), 0, s, y, k, perm, M);
+    else
+        hipLaunchKernelGGL(k_perm_in, dim3(nblk(M * C)), dim3(256), 0, s, y, k, perm, M, C);
     KP_LAUNCH_CHECK();
 }
 void permute_to_caller(const float2* k, float2* y, const int32_t* perm, int64_t M, int C, hipStream_t s) {
@@ -202,9 +232,16 @@ __global__ void k_set_scalar(float* p, float v) { *p = v; }
 __constant__ float c_h[8];
 __constant__ float c_g[8];
 
+// The filter constants live in each device's own copy of c_h / c_g: they are
+// uploaded once per device (the current one), under a lock so that threads
+// driving plans concurrently neither race on the record nor skip a device.
 void upload_wavelet_constants() {
-    static bool done = false;
-    if (done) return;
+    static std::mutex mu;
+    static std::set<int> done;
+    int dev = 0;
+    KP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count(dev)) return;
     auto h = db4_filter_host();
     float hf[8], gf[8];
     for (int t = 0; t < 8; ++t) {
@@ -213,7 +250,7 @@ void upload_wavelet_constants() {
     }
     KP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_h), hf, sizeof(hf)));
     KP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_g), gf, sizeof(gf)));
-    done = true;
+    done.insert(dev);
 }
 
 struct DwtArgs {
