@@ -104,24 +104,90 @@ def measured_traffic(kernel):
         return None
 
 
-def cpu_baseline(cfg, k, x, maps):
-    """The FP64 oracle's NUFFT forward + adjoint on one coil of the workload."""
+_POOL = {}
+
+
+def _coil_worker(c):
+    """One coil of the workload in a forked worker: tap setup (untimed), wait
+    for every worker, then the oracle's forward + adjoint (timed)."""
     from oracle import nufft as onufft
+    cfg, k, x, maps, barrier = (_POOL[n] for n in ("cfg", "k", "x", "maps", "barrier"))
+    op = onufft.Nufft(k, cfg.shape, maps[c:c + 1], cfg.alpha, cfg.width)
+    barrier.wait()
+    t0 = time.perf_counter()
+    y = op.forward(x)
+    op.adjoint(y)
+    return time.perf_counter() - t0
+
+
+def cpu_legs(cfg, k, x, maps, pool_workers):
+    """The FP64 oracle's NUFFT forward + adjoint on the host, before any GPU
+    use (the all-cores leg forks worker processes):
+    * one core: coil 0 of the workload (full 200^3 grid, every sample), tap
+      setup excluded; its outputs also serve as the parity reference;
+    * all cores: the 8 coils in a coil-parallel pool of forked workers, one
+      coil each, timed together after every worker's tap setup."""
+    import multiprocessing as mp
+    from oracle import nufft as onufft
+    M, C = k.shape[0], cfg.ncoils
     t0 = time.perf_counter()
     op = onufft.Nufft(k, cfg.shape, maps[:1], cfg.alpha, cfg.width)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    y = op.forward(x)
+    y0 = op.forward(x)
     t1 = time.perf_counter()
-    op.adjoint(y)
+    xa0 = op.adjoint(y0)
     t2 = time.perf_counter()
-    M = k.shape[0]
-    return {
-        "value": M / (t2 - t0) / 1e6, "unit": "Msamples*coil/s", "cores": 1, "kind": "oracle",
-        "sample": "one of 8 coils of the full workload (full 200^3 grid, all %d samples); "
-                  "forward %.1f s + adjoint %.1f s, tap setup %.1f s excluded; numpy FFT single-threaded"
-                  % (M, t1 - t0, t2 - t1, t_setup),
-    }
+    del op
+    one = {"value": M / (t2 - t0) / 1e6, "unit": "Msamples*coil/s", "cores": 1, "kind": "oracle",
+           "sample": "coil 0 of the workload (full 200^3 grid, all %d samples): forward %.1f s + adjoint %.1f s, "
+                     "tap setup %.1f s excluded; numpy FFT single-threaded" % (M, t1 - t0, t2 - t1, t_setup)}
+    nw = min(C, pool_workers)
+    ctx = mp.get_context("fork")
+    _POOL.update(cfg=cfg, k=k, x=x, maps=maps, barrier=ctx.Barrier(nw))
+    t0 = time.perf_counter()
+    with ctx.Pool(nw) as pool:
+        times = pool.map(_coil_worker, list(range(nw)), chunksize=1)
+    wall = time.perf_counter() - t0
+    _POOL.clear()
+    t_max = max(times)
+    allc = {"value": M * nw / t_max / 1e6, "unit": "Msamples*coil/s", "cores": nw, "kind": "oracle",
+            "sample": "%d of the %d coils of the workload, one per forked worker (full grid, all samples), forward + "
+                      "adjoint timed together after every worker's tap setup: slowest worker %.1f s (pool wall %.1f s "
+                      "incl. setup)" % (nw, C, t_max, wall),
+            "one_core": one}
+    return allc, (y0, xa0)
+
+
+def oracle_small_timings():
+    """The oracle on the two 2D workloads: NUFFT forward + adjoint,
+    preconditioner build (efficient algorithm at 2N) and PDHG iterations
+    (bounded: the 2D spiral solve is timed over 3 power-method and 3 PDHG
+    iterations), single process."""
+    import synth
+    from oracle import nufft as onufft
+    from oracle import pdhg as opdhg
+    from oracle import precond as oprecond
+    out = {}
+    for cid, iters, pits in ((1, 20, 30), (2, 3, 3)):
+        cfg = synth.config(cid)
+        x, maps, k, w = cfg.inputs(seed=cid)
+        op = onufft.Nufft(k, cfg.shape, maps, cfg.alpha, cfg.width)
+        t0 = time.perf_counter()
+        y = op.forward(x)
+        op.adjoint(y)
+        t_pair = time.perf_counter() - t0
+        y = y + w
+        t0 = time.perf_counter()
+        p = oprecond.efficient_nufft(maps if cfg.precond == "mc" else None, k, cfg.shape, cfg.alpha, cfg.width)
+        t_pre = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        opdhg.pdhg(op.forward, op.adjoint, y, p, cfg.shape, cfg.reg, cfg.lam, iters, power_iters=pits, levels=4)
+        t_solve = time.perf_counter() - t0
+        out[cfg.name] = {"nufft_pair_s": round(t_pair, 3), "precond_%s_s" % cfg.precond: round(t_pre, 3),
+                         "solve_s": round(t_solve, 3), "solve_iters": iters, "power_iters": pits,
+                         "msamples_coil_per_s": round(k.shape[0] * cfg.ncoils / t_pair / 1e6, 4), "cores": 1}
+    return out
 
 
 def _events():
@@ -132,6 +198,135 @@ def _events():
 def _rel(a, b):
     import torch
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def bench_small_configs(kp, dev, reps=20):
+    """The two 2D workloads at their full sizes on the GPU (absolute numbers:
+    their grids sit in L2 / Infinity Cache, so they are launch and latency
+    bound): NUFFT forward + adjoint through the C ABI and the PDHG solve of the
+    workload (its regulariser, preconditioner and iteration count)."""
+    import torch
+    import synth
+    out = {}
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    for cid in (1, 2):
+        cfg = synth.config(cid)
+        x, maps, k, w = cfg.inputs(seed=cid)
+        M, C = k.shape[0], cfg.ncoils
+        kt = torch.from_numpy(k).to(dev)
+        mt = None if maps is None else torch.from_numpy(maps.astype(np.complex64)).to(dev)
+        xt = torch.from_numpy(x.astype(np.complex64)).to(dev)
+        hi = kp.nufft_plan(kt, cfg.shape, mt, oversamp=2.0, kb_width=8)
+        y = kp.nufft_forward(hi, xt) + torch.from_numpy(w.astype(np.complex64)).to(dev)
+        hi.close()
+        plan = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
+        kind = kp.KP_PRECOND_MC if cfg.precond == "mc" else kp.KP_PRECOND_SC
+        p = kp.precond_build(plan, kind)
+        lmax = float(kp.pdhg_lambda_max(plan, p, 30).item())
+        ya, xa = torch.empty_like(y), torch.empty_like(xt)
+        for _ in range(3):
+            kp.nufft_forward(plan, xt, ya)
+            kp.nufft_adjoint(plan, ya, xa)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(reps):
+            kp.nufft_forward(plan, xt, ya)
+            kp.nufft_adjoint(plan, ya, xa)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t_pair = e0.elapsed_time(e1) / 1e3 / reps
+        kw = dict(reg=cfg.reg, lam=cfg.lam, iters=cfg.iters, wavelet_levels=4, lambda_max=lmax)
+        kp.pdhg_solve(plan, y, p, **kw)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(5):
+            kp.pdhg_solve(plan, y, p, **kw)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t_solve = e0.elapsed_time(e1) / 1e3 / 5
+        info = plan.info()
+        bm = byte_model(cfg.shape, info["grid"], C, M, cfg.ndim)
+        plan.close()
+        out[cfg.name] = {
+            "nufft_pair_us": round(t_pair * 1e6, 1),
+            "nufft_pair_msamples_coil_per_s": round(M * C / t_pair / 1e6, 1),
+            "nufft_pair_byte_model_frac": round(bm["total"] / t_pair / 1e9 / HBM_PEAK_GBS, 4),
+            "pdhg_iters": cfg.iters, "pdhg_solve_ms": round(t_solve * 1e3, 3),
+            "pdhg_iters_per_s": round(cfg.iters / t_solve, 1),
+            "reg": cfg.reg, "precond": cfg.precond,
+        }
+    return out
+
+
+def copy_bandwidth(dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of `nbytes` (read + write) timed with HIP events."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * nbytes / t / 1e9
+
+
+def gpu_clock():
+    """Current and top shader clock (MHz) from sysfs, best effort."""
+    import glob
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            lines = open(path).read().split("\n")
+        except OSError:
+            continue
+        mhz = []
+        cur = None
+        for ln in lines:
+            parts = ln.replace("Mhz", "").replace("MHz", "").split()
+            if len(parts) >= 2 and parts[1].isdigit():
+                mhz.append(int(parts[1]))
+                if "*" in ln:
+                    cur = int(parts[1])
+        if mhz:
+            return {"sclk_mhz_current": cur, "sclk_mhz_max": max(mhz), "source": path}
+    return None
+
+
+def precond_comparison_3d(kp, plan, y, p_mc, cfg, lmax_mc, dev):
+    """P = I vs SC vs MC on the timed 3D UTE workload (l1-db4, lambda 5e-3):
+    the normalised objective gap (f_k - f*) / (f_0 - f*) at k = 5, 10, 20, 30,
+    f* the least objective of 300 MC-preconditioned iterations, and the time
+    per iteration of each preconditioner (lambda_max by 30 power iterations
+    each, built beforehand; the timed solves have no objective syncs)."""
+    import torch
+    s = torch.cuda.current_stream()
+    e0, e1 = _events()
+    ps = {"none": None, "sc": kp.precond_build(plan, kp.KP_PRECOND_SC), "mc": p_mc}
+    lm = {"none": float(kp.pdhg_lambda_max(plan, None, 30).item()),
+          "sc": float(kp.pdhg_lambda_max(plan, ps["sc"], 30).item()), "mc": lmax_mc}
+    kw = dict(reg=cfg.reg, lam=cfg.lam, wavelet_levels=4)
+    _, ref = kp.pdhg_solve(plan, y, p_mc, iters=300, lambda_max=lm["mc"], objective=True, **kw)
+    fstar = min(ref)
+    comp = {}
+    for name, p in ps.items():
+        _, hist = kp.pdhg_solve(plan, y, p, iters=30, lambda_max=lm[name], objective=True, **kw)
+        torch.cuda.synchronize()
+        e0.record(s)
+        kp.pdhg_solve(plan, y, p, iters=30, lambda_max=lm[name], **kw)
+        e1.record(s)
+        torch.cuda.synchronize()
+        gap = [(h - fstar) / (hist[0] - fstar) for h in hist]
+        comp[name] = {"gap_at": {str(i): float("%.4g" % gap[i]) for i in (5, 10, 20, 30)},
+                      "ms_per_iter": round(e0.elapsed_time(e1) / 30, 4), "lambda_max": round(lm[name], 6)}
+    return {"workload": cfg.name + ", l1-db4 lambda 5e-3, 30 iterations",
+            "reference": "f* = least objective of 300 MC-preconditioned iterations", "gap": comp}
 
 
 def bench_batched(kp, dev, reps=3):
@@ -217,7 +412,7 @@ def bench_differentiable(kp, dev, reps=3):
     against the plain 10-iteration pdhg_solve of the same slices."""
     import torch
     import synth
-    from paper_1902_09657_amd.autograd import schedule_params, unrolled_pdhg
+    from paper_1902_09657_amd.autograd import schedule_params, unrolled_pdhg, unrolled_pdhg_batch
     cfg = synth.config(5)
     K, C, nb = cfg.iters, cfg.ncoils, cfg.extra["batch"]
     log("differentiable: inputs for", nb, "slices")
@@ -239,17 +434,27 @@ def bench_differentiable(kp, dev, reps=3):
     params = [schedule_params(pl, ps[i], K, lam=cfg.lam, lambda_max=lms[i]) for i, pl in enumerate(plans)]
 
     def step():
+        # one forward + backward over the 8 slices as one batch (slices run
+        # concurrently on side streams); loss = sum of the slices' losses
+        ths = [pr.detach().clone().requires_grad_(True) for pr in params]
+        xks = unrolled_pdhg_batch(ys, ths, plans, ps, K)
         loss = 0.0
-        xs = []
+        for i, xk in enumerate(xks):
+            r = xk - xt[i]
+            loss = loss + 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+        loss.backward()
+        return [xk.detach() for xk in xks], loss.detach(), [th.grad for th in ths]
+
+    def step_sequential():
+        # the same, slice after slice through the single-slice Function
+        out = []
         for i, pl in enumerate(plans):
             th = params[i].detach().clone().requires_grad_(True)
             xk = unrolled_pdhg(ys[i], th, pl, ps[i], K)
             r = xk - xt[i]
-            li = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
-            li.backward()
-            loss = loss + li.detach()
-            xs.append(xk.detach())
-        return xs, loss
+            (0.5 * (r.real ** 2 + r.imag ** 2).sum()).backward()
+            out.append(th.grad)
+        return out
 
     s = torch.cuda.current_stream()
     e0, e1 = _events()
@@ -257,10 +462,19 @@ def bench_differentiable(kp, dev, reps=3):
     torch.cuda.synchronize()
     e0.record(s)
     for _ in range(reps):
-        xs, loss = step()
+        xs, loss, grads = step()
     e1.record(s)
     torch.cuda.synchronize()
     t_fb = e0.elapsed_time(e1) / 1e3 / reps
+    step_sequential()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        grads_seq = step_sequential()
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) / 1e3 / reps
+    gdiff = max(_rel(a, b) for a, b in zip(grads, grads_seq))
     xp = [kp.pdhg_solve(pl, ys[i], ps[i], reg="l2", lam=cfg.lam, iters=K, lambda_max=lms[i])
           for i, pl in enumerate(plans)]
     torch.cuda.synchronize()
@@ -278,8 +492,9 @@ def bench_differentiable(kp, dev, reps=3):
     return {
         "workload": cfg.name + " x%d slices, %d-step unrolled l2 PDHG, learnable steps and lambda" % (nb, K),
         "fwd_bwd_ms": round(t_fb * 1e3, 3), "plain_solve_ms": round(t_p * 1e3, 3),
-        "fwd_bwd_over_plain": round(t_fb / t_p, 3), "loss": float(loss.item()),
-        "ckpt_bytes_per_slice": int(ck), "max_rel_diff_forward_vs_plain": diff,
+        "fwd_bwd_over_plain": round(t_fb / t_p, 3), "fwd_bwd_ms_slice_after_slice": round(t_seq * 1e3, 3),
+        "loss": float(loss.item()), "ckpt_bytes_per_slice": int(ck), "max_rel_diff_forward_vs_plain": diff,
+        "max_rel_diff_grad_batch_vs_slice_after_slice": gdiff,
     }
 
 
@@ -390,7 +605,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle legs (cpu_baseline, the parity gate and the oracle timings)")
+    ap.add_argument("--pool-workers", type=int, default=16, help="processes of the all-cores oracle leg (at most)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and differentiable forms")
     ap.add_argument("--profile-stages", type=int, default=0, metavar="R",
@@ -405,20 +622,33 @@ def main():
               "single-GPU workload); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import synth
+    cfg = synth.config(3)
+    cpu, ref, oracle_t = None, None, None
+    if not args.form_only and not args.profile_stages:
+        log("generating inputs", cfg.name)
+        x, maps, k, w = cfg.inputs(seed=3)
+        if not args.no_cpu_baseline:
+            # the oracle legs run before anything touches the GPU (the
+            # all-cores leg forks worker processes)
+            log("cpu baseline: oracle, one core and a coil-parallel pool")
+            workers = max(1, min(args.pool_workers, len(os.sched_getaffinity(0))))
+            cpu, ref = cpu_legs(cfg, k, x, maps, workers)
+            log("oracle timings of the 2D workloads")
+            oracle_t = oracle_small_timings()
+
     import torch
     import paper_1902_09657_amd as kp
     from paper_1902_09657_amd import _lib
-    import synth
 
     dev = torch.device("cuda:0")
     if args.form_only:
         fn = bench_batched if args.form_only == "batched" else bench_differentiable
         print(json.dumps(fn(kp, dev)), flush=True)
         return
-    cfg = synth.config(3)
     d = cfg.ndim
-    log("generating inputs", cfg.name)
-    x, maps, k, w = cfg.inputs(seed=3)
+    if args.profile_stages:
+        x, maps, k, w = cfg.inputs(seed=3)
     M, C = k.shape[0], cfg.ncoils
     xt = torch.from_numpy(x.astype(np.complex64)).to(dev)
     mt = torch.from_numpy(maps.astype(np.complex64)).to(dev)
@@ -456,6 +686,26 @@ def main():
     t_plan = time.perf_counter() - t0
     info = plan.info()
     log("plan info", info)
+
+    # accuracy gate: coil 0 of the timed plan's forward, and its adjoint of
+    # coil-0 data, against the oracle outputs of the one-core leg
+    parity = None
+    if ref is not None:
+        log("parity gate")
+        y0, xa0 = ref
+        yg = kp.nufft_forward(plan, xt)[0].cpu().numpy()
+        yin = torch.zeros((C, M), dtype=torch.complex64, device=dev)
+        yin[0] = torch.from_numpy(y0[0].astype(np.complex64)).to(dev)
+        xg = kp.nufft_adjoint(plan, yin).cpu().numpy()
+        e_f = float(np.linalg.norm(yg - y0[0]) / np.linalg.norm(y0[0]))
+        e_a = float(np.linalg.norm(xg - xa0) / np.linalg.norm(xa0))
+        parity = {"forward_coil0_rel_l2": e_f, "adjoint_coil0_rel_l2": e_a, "gate": 1e-4,
+                  "reference": "FP64 oracle (one-core leg)"}
+        del yin
+        if not (e_f <= 1e-4 and e_a <= 1e-4):
+            print("bench.py: parity gate failed (forward %.3e, adjoint %.3e > 1e-4): no result" % (e_f, e_a),
+                  file=sys.stderr, flush=True)
+            sys.exit(3)
 
     log("precond")
     t0 = time.perf_counter()
@@ -542,6 +792,10 @@ def main():
     achieved = bm[dom] / (kernel_ms[dom] / 1e3) / 1e9
     traffic = measured_traffic(dom)
 
+    # the box's own copy bandwidth and shader clock, for context
+    bw_copy = copy_bandwidth(dev)
+    clock = gpu_clock()
+
     K = args.steps
     value = M * C * K / t_solve / 1e6
     result = {
@@ -559,12 +813,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name, "image": list(cfg.shape), "coils": C, "samples_per_coil": M,
                    "oversamp": cfg.alpha, "kb_width": cfg.width, "reg": "l1-db4-4lev", "lambda": cfg.lam,
-                   "precond": "mc", "iters": K},
+                   "precond": "mc", "iters": cfg.iters, "timed_iterations": K},
         "pdhg_iters_per_s": round(K / t_solve, 2),
         "tv_ms_per_step": round(t_tv / K * 1e3, 4),
         "nufft_pair_ms": round(t_pair * 1e3, 4),
         "nufft_pair_msamples_coil_per_s": round(M * C / t_pair / 1e6, 2),
         "nufft_pair_hbm_roofline_frac": round(bm["total"] / t_pair / 1e9 / HBM_PEAK_GBS, 4),
+        "nufft_pair_byte_model_bytes": int(bm["total"]),
+        "copy_bandwidth_gbs": round(bw_copy, 1),
+        "nufft_pair_frac_of_copy_bandwidth": round(bm["total"] / t_pair / 1e9 / bw_copy, 4),
+        "gpu_clock": clock,
+        "parity": parity,
         "stage_ms": {k2: round(v, 4) for k2, v in stage_ms.items()},
         "setup_s": {"plan": round(t_plan, 4), "precond_mc": round(t_pre, 4), "lambda_max_30": round(t_lmax, 4)},
         "lambda_max": lmax_v,
@@ -573,15 +832,23 @@ def main():
                      "algorithmic_bytes": int(bm[dom]), "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
     }
+    ctx3 = None
+    if not args.no_forms:
+        log("3D preconditioner comparison")
+        ctx3 = precond_comparison_3d(kp, plan, y, p, cfg, lmax_v, dev)
     plan.close()
     del plan
     if not args.no_forms:
+        log("2D workloads")
+        result["small_configs"] = bench_small_configs(kp, dev)
         result["batched"] = bench_batched(kp, dev)
         result["differentiable"] = bench_differentiable(kp, dev)
         result["context"] = bench_context(kp, dev)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, one coil)")
-        result["cpu_baseline"] = cpu_baseline(cfg, k, x, maps)
+        result["context"]["precond_comparison_3d"] = ctx3
+    if oracle_t is not None:
+        result.setdefault("context", {})["oracle_timings_2d"] = oracle_t
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

@@ -1,9 +1,10 @@
 // Batched form: many independent 2D slices with uneven image sizes and
-// trajectories solved together.  Every phase of a PDHG iteration (forward
-// FFT passes, interpolation with the dual update, spreading, partial-tile
-// reduction, inverse FFT passes with the primal update) is ONE kernel launch
-// over all slices, driven by per-slice descriptor tables; the whole K
-// iteration loop is captured once into a HIP graph and replayed.
+// trajectories solved together.  Every phase of a PDHG iteration (each of the
+// two forward FFT passes, interpolation with the dual update, spreading,
+// partial-tile reduction, each of the two inverse FFT passes with the primal
+// update) is ONE kernel launch over all slices and grid lengths, driven by
+// per-slice descriptor tables; the whole K iteration loop is captured once
+// into a HIP graph and replayed.
 //
 // Tile shapes and split sizes come from a small autotuner that times the
 // spreading and interpolation kernels of candidate tilings on each slice
@@ -154,10 +155,10 @@ static DescLayout desc_layout(int n, int K, int nh) {
     L.sp = take(sizeof(SpreadArgs) * n);
     L.hv = take(sizeof(int2) * std::max(nh, 1));
     L.hl = take(sizeof(int4*) * n);
-    L.sfA = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
-    L.sfB = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
-    L.saA = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
-    L.saB = take(sizeof(int64_t) * (2 * n + 1));  // one relative array per length group
+    L.sfA = take(sizeof(int64_t) * (n + 1));
+    L.sfB = take(sizeof(int64_t) * (n + 1));
+    L.saA = take(sizeof(int64_t) * (n + 1));
+    L.saB = take(sizeof(int64_t) * (n + 1));
     L.sit = take(sizeof(int64_t) * (n + 1));
     L.ssp = take(sizeof(int64_t) * (n + 1));
     L.total = o;
@@ -214,42 +215,41 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
         spread_thr = std::max(spread_thr, ((spread_threads(2, P.Bs, C) + 63) / 64) * 64);
         spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C, kZMax));
     }
-    // FFT launches per transform length: slices sorted by G, one launch per
-    // group and phase, LDS sized for the group's own length; lines longer
-    // than 206 use 16-column blocks (54 KB of LDS at 400) so that every
-    // group keeps several resident blocks per CU
+    // FFT phases: one persistent launch each over the passes of every slice,
+    // sorted by transform length; lines longer than 206 rows use 16-column
+    // blocks (54 KB of LDS at 400) and shorter ones 32 (the passes along the
+    // coils keep the coil count as their column block), LDS sized for the
+    // largest column block of the phase
     std::vector<int> ord(n);
     for (int i = 0; i < n; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return B.plans[x]->G[0] < B.plans[y]->G[0]; });
-    struct Group { int j0, j1, L, ncw; };
-    std::vector<Group> groups;
-    for (int j = 0; j < n; ++j) {
-        const int Lj = B.plans[ord[j]]->G[0];
-        if (groups.empty() || groups.back().L != Lj) groups.push_back({j, j, Lj, Lj <= 206 ? 32 : 16});
-        groups.back().j1 = j + 1;
-    }
-    auto narrow = [](FftPass fp, int ncw) {
-        if (fp.Ob == 1 && fp.Ib == 32 && ncw == 16) fp.Ib = 16;
-        return fp;
-    };
+    struct Phase { int map; size_t lds; };
+    Phase ph[4];
     {
         std::vector<FftPass> tA(n), tB(n), tC(n), tD((size_t)n * K);
-        std::vector<int64_t> cA(2 * n + 1, 0), cB(2 * n + 1, 0), cC(2 * n + 1, 0), cD(2 * n + 1, 0);
-        for (size_t g = 0; g < groups.size(); ++g) {
-            const Group& G = groups[g];
-            const size_t base = (size_t)G.j0 + g;  // the group's relative block-start array
-            for (int j = G.j0; j < G.j1; ++j) {
-                const int i = ord[j];
-                tA[j] = narrow(fA[i], G.ncw);
-                tB[j] = narrow(fB[i], G.ncw);
-                tC[j] = narrow(aA[i], G.ncw);
-                for (int k = 0; k < K; ++k) tD[(size_t)k * n + j] = narrow(aB[(size_t)k * n + i], G.ncw);
-                const size_t r = base + (j - G.j0);
-                cA[r + 1] = cA[r] + fft_pass_blocks(tA[j]);
-                cB[r + 1] = cB[r] + fft_pass_blocks(tB[j]);
-                cC[r + 1] = cC[r] + fft_pass_blocks(tC[j]);
-                cD[r + 1] = cD[r] + fft_pass_blocks(tD[j]);
-            }
+        std::vector<int64_t> cA(n + 1, 0), cB(n + 1, 0), cC(n + 1, 0), cD(n + 1, 0);
+        // the map passes (fA, aB) run along the coils: their column block is
+        // the same for every slice
+        const int nc_map[4] = {fA[0].Ob * fA[0].Ib, 0, 0, aB[0].Ob * aB[0].Ib};
+        auto shape = [&](FftPass fp, int q) {
+            const int nc = fft_mixed_columns(fp.L, nc_map[q]);
+            if (nc_map[q] == 0 && fp.Ob == 1) fp.Ib = nc;
+            return fp;
+        };
+        for (int q = 0; q < 4; ++q) ph[q] = Phase{nc_map[q], 0};
+        for (int j = 0; j < n; ++j) {
+            const int i = ord[j];
+            tA[j] = shape(fA[i], 0);
+            tB[j] = shape(fB[i], 1);
+            tC[j] = shape(aA[i], 2);
+            for (int k = 0; k < K; ++k) tD[(size_t)k * n + j] = shape(aB[(size_t)k * n + i], 3);
+            cA[j + 1] = cA[j] + fft_pass_blocks(tA[j]);
+            cB[j + 1] = cB[j] + fft_pass_blocks(tB[j]);
+            cC[j + 1] = cC[j] + fft_pass_blocks(tC[j]);
+            cD[j + 1] = cD[j] + fft_pass_blocks(tD[j]);
+            const FftPass* t4[4] = {&tA[j], &tB[j], &tC[j], &tD[j]};
+            for (int q = 0; q < 4; ++q)
+                ph[q].lds = std::max(ph[q].lds, sizeof(float2) * (size_t)t4[q]->L * (t4[q]->Ob * t4[q]->Ib + 1));
         }
         fA.swap(tA);
         fB.swap(tB);
@@ -275,24 +275,17 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
     up(L.sp, sp.data(), sizeof(SpreadArgs) * n);
     up(L.hv, hv.data(), sizeof(int2) * nh);
     up(L.hl, hl.data(), sizeof(int4*) * n);
-    up(L.sfA, sfA.data(), sizeof(int64_t) * (2 * n + 1));
-    up(L.sfB, sfB.data(), sizeof(int64_t) * (2 * n + 1));
-    up(L.saA, saA.data(), sizeof(int64_t) * (2 * n + 1));
-    up(L.saB, saB.data(), sizeof(int64_t) * (2 * n + 1));
+    up(L.sfA, sfA.data(), sizeof(int64_t) * (n + 1));
+    up(L.sfB, sfB.data(), sizeof(int64_t) * (n + 1));
+    up(L.saA, saA.data(), sizeof(int64_t) * (n + 1));
+    up(L.saB, saB.data(), sizeof(int64_t) * (n + 1));
     up(L.sit, sit.data(), sizeof(int64_t) * (n + 1));
     up(L.ssp, ssp.data(), sizeof(int64_t) * (n + 1));
     const KbParams kb = B.plans[0]->kb;
-    // one launch per length group: passes [j0, j1) of a phase table, with the
-    // group's relative block starts
-    auto fft_phase = [&](size_t tab, size_t starts, const std::vector<FftPass>& t, const std::vector<int64_t>& st,
-                         size_t shift) {
-        for (size_t g = 0; g < groups.size(); ++g) {
-            const Group& G = groups[g];
-            const size_t base = (size_t)G.j0 + g;
-            const int ng = G.j1 - G.j0;
-            launch_fft_batch((const FftPass*)(d + tab) + shift + G.j0, (const int64_t*)(d + starts) + base, ng,
-                             st[base + ng], G.L, t[shift + G.j0].Ob * t[shift + G.j0].Ib, B.cap);
-        }
+    // one launch per FFT phase over every slice's pass
+    auto fft_phase = [&](size_t tab, size_t starts, const std::vector<int64_t>& st, size_t shift, const Phase& q) {
+        launch_fft_batch_mixed((const FftPass*)(d + tab) + shift, (const int64_t*)(d + starts), n, st[n], q.map, q.lds,
+                               B.cap);
     };
 
     if (B.exec) (void)hipGraphExecDestroy(B.exec);
@@ -302,16 +295,16 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
     KP_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeRelaxed));
     try {
         for (int k = 0; k < K; ++k) {
-            fft_phase(L.fA, L.sfA, fA, sfA, 0);
-            fft_phase(L.fB, L.sfB, fB, sfB, 0);
+            fft_phase(L.fA, L.sfA, sfA, 0, ph[0]);
+            fft_phase(L.fB, L.sfB, sfB, 0, ph[1]);
             launch_interp_batch((const InterpArgs*)(d + L.it) + (size_t)k * n, (const int64_t*)(d + L.sit), n, sit[n],
                                 kb, B.cap);
             launch_spread_batch((const SpreadArgs*)(d + L.sp), (const int64_t*)(d + L.ssp), n, ssp[n], spread_thr,
                                 spread_lds, kb, B.cap);
             launch_reduce_batch((const SpreadArgs*)(d + L.sp), (const int2*)(d + L.hv), (const int4* const*)(d + L.hl),
                                 nh, B.cap);
-            fft_phase(L.aA, L.saA, aA, saA, 0);
-            fft_phase(L.aB, L.saB, aB, saB, (size_t)k * n);
+            fft_phase(L.aA, L.saA, saA, 0, ph[2]);
+            fft_phase(L.aB, L.saB, saB, (size_t)k * n, ph[3]);
         }
     } catch (...) {
         hipGraph_t g = nullptr;

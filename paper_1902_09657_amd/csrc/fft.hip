@@ -365,6 +365,22 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
         xlo = r.x;
         xhi = r.y;
     }
+    // y-range pruning: on an axis-0 pass this thread's column (y, z) may lie
+    // outside the y-range of its z (col_out); on an axis-1 pass the rows
+    // [ylo, yhi) of its z are the ones that matter
+    int ylo = 0, yhi = L;
+    bool col_out = false;
+    if (p.yr_mode && live) {
+        const int zz = (int)((i % p.xr_G2C) / p.xr_C);
+        const int2 r = p.yr[zz / p.xr_B2];
+        if (p.yr_mode <= 2) {
+            const int64_t yy = i / p.xr_G2C;
+            col_out = !(yy >= r.x && yy < r.y);
+        } else {
+            ylo = r.x;
+            yhi = r.y;
+        }
+    }
 
     // ---- load (pruned): every row load of this thread is issued before the
     // first LDS write, so the block has all its loads in flight at once
@@ -373,18 +389,25 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
     constexpr int NR = (L + RS - 1) / RS;
     float2 v[NR];
     const int64_t oc = live ? o : 0, ic = live ? i : 0;
-    if (p.pre == PRE_NONE && p.xr_mode == 2) {
-        // rows outside the support range are zero (spreading leaves them empty)
+    if (p.pre == PRE_NONE && (p.xr_mode == 2 || p.yr_mode == 4)) {
+        // rows outside the support range are zero (spreading leaves them
+        // empty, or the previous pass did not store them) and are not loaded
+        const int lo = p.xr_mode == 2 ? xlo : ylo, hi = p.xr_mode == 2 ? xhi : yhi;
         const float2* src = p.in + oc * p.in_os + ic;
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int r = min(rb + k * RS, p.Lin - 1);
-            v[k] = (r >= xlo && r < xhi) ? src[(int64_t)r * p.in_rs] : make_float2(0.f, 0.f);
+            v[k] = (r >= lo && r < hi) ? src[(int64_t)r * p.in_rs] : make_float2(0.f, 0.f);
         }
     } else if (p.pre == PRE_NONE) {
         const float2* src = p.in + oc * p.in_os + ic;
+        if (col_out) {  // a column nothing reads (yr_mode 1): not loaded
 #pragma unroll
-        for (int k = 0; k < NR; ++k) v[k] = src[(int64_t)min(rb + k * RS, p.Lin - 1) * p.in_rs];
+            for (int k = 0; k < NR; ++k) v[k] = make_float2(0.f, 0.f);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) v[k] = src[(int64_t)min(rb + k * RS, p.Lin - 1) * p.in_rs];
+        }
     } else if (p.pre == PRE_MAPS) {
         float2 mv[NR];
         float fr[NR];
@@ -475,8 +498,10 @@ __device__ __forceinline__ void fft_fixed_body(const FftPass& p, int64_t bid, fl
         return;
     }
     if (!live) return;
+    if (p.yr_mode == 2 && col_out) return;  // an empty column: the next pass takes it as zero
     for (int m = rb; m < p.Lout; m += RS) {
         if (p.xr_mode == 1 && (m < xlo || m >= xhi)) continue;  // nothing reads these rows
+        if (p.yr_mode == 3 && (m < ylo || m >= yhi)) continue;  // rows of empty columns
         int q = m;
         if (p.crop_out) {
             q = m - p.Lout / 2;
@@ -504,33 +529,81 @@ __global__ void __launch_bounds__(NT) k_fft_fixed(FftPass p) {
 // lines).  32 columns = 256 contiguous bytes per row.
 static int fixed_threads(int nc) { return nc == 12 ? 384 : ((nc == 8 || nc == 16 || nc == 32) ? 256 : 0); }
 
-// One launch over the passes of many independent transforms (the slices of a
-// batch): block b runs pass s with blk_start[s] <= b < blk_start[s+1].  All
-// passes of one launch share the column block (NC, NT).  The 12-, 16- and
-// 32-column blocks run on twice the threads of the single-transform kernels
-// (384, 512, 512): each thread then holds half as many rows of the long 2D
-// lines, and the batched solve ran 7 % faster (four times the threads: 4 %).
-template <int NC, int NT>
-__global__ void __launch_bounds__(NT) k_fft_batch(const FftPass* __restrict__ passes,
-                                                   const int64_t* __restrict__ blk_start, int n) {
+// One launch over the passes of many independent transforms of mixed lengths
+// (one phase of the slices of a batch): pass s owns the blocks
+// blk_start[s] .. blk_start[s+1]-1 (passes sorted by length).  Each length
+// has its own column block: the coil block of the passes along the coils
+// (MAP > 0), else kMixCols(L), chosen so that every length needs at most
+// about 43 KB of LDS (three resident blocks per CU); LDS is sized for the
+// largest of them.
+__host__ __device__ constexpr int kMixCols(int L) { return L <= 206 ? 32 : (L <= 320 ? 16 : 8); }
+
+template <int NT, int MAP, int L>
+__device__ __forceinline__ void mixed_body(const FftPass& p, int64_t bid, float2* buf) {
+    constexpr int NC = MAP > 0 ? MAP : kMixCols(L);
+    fft_fixed_body<L, NC, NT>(p, bid, buf);
+}
+
+template <int NT, int MAP>
+__global__ void __launch_bounds__(NT) k_fft_batch_mixed(const FftPass* __restrict__ passes,
+                                                         const int64_t* __restrict__ blk_start, int n) {
     extern __shared__ float2 buf[];
-    const int64_t b = blockIdx.x;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {  // last s with blk_start[s] <= b
-        const int mid = (lo + hi + 1) / 2;
-        if (blk_start[mid] <= b) lo = mid; else hi = mid - 1;
+    {
+        const int64_t b = blockIdx.x;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {  // last s with blk_start[s] <= b
+            const int mid = (lo + hi + 1) / 2;
+            if (blk_start[mid] <= b) lo = mid; else hi = mid - 1;
+        }
+        const FftPass p = passes[lo];
+        const int64_t bid = b - blk_start[lo];
+        switch (p.L) {
+            case 160: mixed_body<NT, MAP, 160>(p, bid, buf); break;
+            case 200: mixed_body<NT, MAP, 200>(p, bid, buf); break;
+            case 240: mixed_body<NT, MAP, 240>(p, bid, buf); break;
+            case 256: mixed_body<NT, MAP, 256>(p, bid, buf); break;
+            case 320: mixed_body<NT, MAP, 320>(p, bid, buf); break;
+            case 400: mixed_body<NT, MAP, 400>(p, bid, buf); break;
+            default: break;
+        }
     }
-    const FftPass p = passes[lo];
-    const int64_t bid = b - blk_start[lo];
-    switch (p.L) {
-        case 160: fft_fixed_body<160, NC, NT>(p, bid, buf); break;
-        case 200: fft_fixed_body<200, NC, NT>(p, bid, buf); break;
-        case 240: fft_fixed_body<240, NC, NT>(p, bid, buf); break;
-        case 256: fft_fixed_body<256, NC, NT>(p, bid, buf); break;
-        case 320: fft_fixed_body<320, NC, NT>(p, bid, buf); break;
-        case 400: fft_fixed_body<400, NC, NT>(p, bid, buf); break;
-        default: break;
+}
+
+// the kernel of a phase (map = the coil column block of the passes along the
+// coils, 0 for the others) and its thread count
+static const void* mixed_kernel(int map, int* nt) {
+    switch (map) {
+        case 0: *nt = 512; return (const void*)k_fft_batch_mixed<512, 0>;
+        case 8: *nt = 256; return (const void*)k_fft_batch_mixed<256, 8>;
+        case 12: *nt = 384; return (const void*)k_fft_batch_mixed<384, 12>;
+        case 16: *nt = 512; return (const void*)k_fft_batch_mixed<512, 16>;
+        default: return nullptr;
     }
+}
+
+int fft_mixed_columns(int L, int nc_map) { return nc_map > 0 ? nc_map : kMixCols(L); }
+
+void launch_fft_batch_mixed(const FftPass* d_passes, const int64_t* d_blk_start, int n, int64_t nblk, int map,
+                            size_t lds, hipStream_t s) {
+    if (nblk <= 0) return;
+    int nt = 0;
+    const void* fn = mixed_kernel(map, &nt);
+    if (!fn) fail(KP_ERR_UNSUPPORTED, "no mixed-length FFT kernel for this column block");
+    if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "batched FFT grid too large");
+    if (lds > 65536) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    const dim3 g((unsigned)nblk);
+    if (map == 0)
+        hipLaunchKernelGGL((k_fft_batch_mixed<512, 0>), g, dim3(512), lds, s, d_passes, d_blk_start, n);
+    else if (map == 8)
+        hipLaunchKernelGGL((k_fft_batch_mixed<256, 8>), g, dim3(256), lds, s, d_passes, d_blk_start, n);
+    else if (map == 12)
+        hipLaunchKernelGGL((k_fft_batch_mixed<384, 12>), g, dim3(384), lds, s, d_passes, d_blk_start, n);
+    else
+        hipLaunchKernelGGL((k_fft_batch_mixed<512, 16>), g, dim3(512), lds, s, d_passes, d_blk_start, n);
+    KP_LAUNCH_CHECK();
 }
 
 static bool batch_length(int L) { return L == 160 || L == 200 || L == 240 || L == 256 || L == 320 || L == 400; }
@@ -545,29 +618,6 @@ bool fft_batchable(const FftPass& p) {
 
 int64_t fft_pass_blocks(const FftPass& p) {
     return ((p.I + p.Ib - 1) / p.Ib) * ((p.O + p.Ob - 1) / p.Ob);
-}
-
-void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n, int64_t nblk, int maxL, int nc,
-                      hipStream_t s) {
-    if (nblk <= 0) return;
-    const size_t lds = sizeof(float2) * (size_t)maxL * (nc + 1);
-    const void* fn = nc == 12   ? (const void*)k_fft_batch<12, 384>
-                     : nc == 32 ? (const void*)k_fft_batch<32, 512>
-                     : nc == 8  ? (const void*)k_fft_batch<8, 256>
-                                : (const void*)k_fft_batch<16, 512>;
-    if (lds > 65536) {
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipGetLastError();
-    }
-    if (nc == 12)
-        hipLaunchKernelGGL((k_fft_batch<12, 384>), dim3((unsigned)nblk), dim3(384), lds, s, d_passes, d_blk_start, n);
-    else if (nc == 32)
-        hipLaunchKernelGGL((k_fft_batch<32, 512>), dim3((unsigned)nblk), dim3(512), lds, s, d_passes, d_blk_start, n);
-    else if (nc == 8)
-        hipLaunchKernelGGL((k_fft_batch<8, 256>), dim3((unsigned)nblk), dim3(256), lds, s, d_passes, d_blk_start, n);
-    else
-        hipLaunchKernelGGL((k_fft_batch<16, 512>), dim3((unsigned)nblk), dim3(512), lds, s, d_passes, d_blk_start, n);
-    KP_LAUNCH_CHECK();
 }
 
 typedef void (*fft_kernel_t)(FftPass);
@@ -625,11 +675,11 @@ void launch_fft_pass(const FftPass& pin, hipStream_t s) {
     const int lim = lds_limit();
     // a small transform (a 2D slice) has too few 32-column blocks to fill the
     // GPU: narrower blocks (16, 8 columns) until the pass has 1024 of them
-    if (p.Ob == 1 && p.Ib == 32 && p.xr_mode == 0 && p.pre != PRE_MAPS && p.post != POST_MAPS)
+    if (p.Ob == 1 && p.Ib == 32 && p.xr_mode == 0 && p.yr_mode == 0 && p.pre != PRE_MAPS && p.post != POST_MAPS)
         while (p.Ib > 8 && fft_pass_blocks(p) < 1024) p.Ib /= 2;
     if (launch_fixed(p, s, lim)) return;
     // support-pruned loads exist only in the specialised kernel
-    if (p.xr_mode == 2) fail(KP_ERR_UNSUPPORTED, "support-pruned FFT pass needs the specialised kernel");
+    if (p.xr_mode == 2 || p.yr_mode == 4) fail(KP_ERR_UNSUPPORTED, "support-pruned FFT pass needs the specialised kernel");
     // shrink the column block until both LDS buffers fit
     while (fft_lds_bytes(p.L, p.Ob * p.Ib) > (size_t)lim) {
         if (p.Ob > 1)

@@ -79,18 +79,29 @@ void kb_fit(double beta, int W, KbParams* kb) {
             }
         }
         for (int k = 0; k < n; ++k) kb->poly[t][k] = (float)(A[k][n] / A[k][k]);
+        if (2 * t < W) {
+            for (int k = 0; k < kHalfN; ++k) {
+                kb->ev[t][k] = (float)(A[2 * k][n] / A[2 * k][2 * k]);
+                kb->od[t][k] = (float)(A[2 * k + 1][n] / A[2 * k + 1][2 * k + 1]);
+            }
+        }
     }
 }
 
 template <int W>
 __device__ __forceinline__ void tap_weights(float frac, const KbParams& kb, float* w) {
     const float x = frac - 0.5f;
+    const float x2 = x * x;
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-        float acc = kb.poly[t][kPolyN - 1];
+    for (int t = 0; t < W / 2; ++t) {  // mirrored pairs (t, W-1-t)
+        float e = kb.ev[t][kHalfN - 1], o = kb.od[t][kHalfN - 1];
 #pragma unroll
-        for (int k = kPolyN - 2; k >= 0; --k) acc = fmaf(acc, x, kb.poly[t][k]);
-        w[t] = acc;
+        for (int k = kHalfN - 2; k >= 0; --k) {
+            e = fmaf(e, x2, kb.ev[t][k]);
+            o = fmaf(o, x2, kb.od[t][k]);
+        }
+        w[t] = fmaf(x, o, e);
+        w[W - 1 - t] = fmaf(-x, o, e);
     }
     if (frac == 0.f) w[W - 1] = 0.f;  // strict support |u| < W/2
 }
@@ -220,7 +231,8 @@ __device__ __forceinline__ int batch_slot(const int64_t* start, int n, int64_t b
     return lo;
 }
 
-// interpolation of many slices in one launch (2D, width 4, coil groups of 4)
+// interpolation of many slices in one launch (2D, width 4, coil groups of 4):
+// the threads of slice s are blocks start[s] .. start[s+1]-1
 __global__ void __launch_bounds__(256) k_interp_batch(const InterpArgs* __restrict__ args,
                                                       const int64_t* __restrict__ start, int n, KbParams kb) {
     const int s = batch_slot(start, n, blockIdx.x);
@@ -231,6 +243,7 @@ __global__ void __launch_bounds__(256) k_interp_batch(const InterpArgs* __restri
 void launch_interp_batch(const InterpArgs* d_args, const int64_t* d_start, int n, int64_t nblk, const KbParams& kb,
                          hipStream_t s) {
     if (nblk <= 0) return;
+    if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "batched interpolation grid too large");
     hipLaunchKernelGGL(k_interp_batch, dim3((unsigned)nblk), dim3(256), 0, s, d_args, d_start, n, kb);
     KP_LAUNCH_CHECK();
 }
@@ -386,8 +399,9 @@ __device__ __forceinline__ float dpp_row_shr2(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
 }
 
-constexpr int kTlBatch = 256;  // samples whose weights sit in LDS at a time
-constexpr int kTlStage = 12;   // halo loads per thread held in registers
+constexpr int kTlThreads = 512;        // threads per block of the tap-lane interpolation
+constexpr int kTlBatch = kTlThreads;   // samples whose weights sit in LDS at a time
+constexpr int kTlStage = 12;           // halo loads per thread held in registers
 constexpr int kTlCG = 4;       // coils per block of the tap-lane interpolation
 
 __host__ __device__ inline int tl_h2p(int H2) { return H2 + ((12 - H2 % 8) % 8); }
@@ -396,7 +410,7 @@ __host__ __device__ inline int tl_h2p(int H2) { return H2 + ((12 - H2 % 8) % 8);
 // arguments).  With constants every halo index is a multiply-shift and the
 // 16 tap offsets fold into the LDS instructions' immediate offsets.
 template <int TB0, int TB1, int TB2, int CG>
-__global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
+__global__ void __launch_bounds__(kTlThreads) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
     static_assert(CG == 2 || CG == 4, "coil groups of 2 or 4");
     constexpr int NP = CG / 2;          // float4 (two coils) per cell
     constexpr int SPW = 64 / (4 * CG);  // samples per wave
@@ -460,7 +474,7 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
     } else {
 #pragma unroll
         for (int r = 0; r < kTlStage; ++r) {
-            const int i = tid + r * 256;
+            const int i = tid + r * kTlThreads;
             if (i < hcells * NP) {
                 const int cell = i / NP, part = i % NP;
                 const int h2 = cell % H2, h01 = cell / H2, h1 = h01 % H1, h0 = h01 / H1;
@@ -515,7 +529,7 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
         } else if (b0 == 0) {
 #pragma unroll
             for (int r = 0; r < kTlStage; ++r) {
-                const int i = tid + r * 256;
+                const int i = tid + r * kTlThreads;
                 if (i < hcells * NP) {
                     const int cell = i / NP, part = i % NP;
                     const int h2 = cell % H2, h01 = cell / H2;
@@ -527,7 +541,7 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
         }
         __syncthreads();
         // ---- one sample per group of 4 CG lanes
-        for (int i = wave * SPW + sub; i < nbt; i += 4 * SPW) {
+        for (int i = wave * SPW + sub; i < nbt; i += (kTlThreads / 64) * SPW) {
             float* row = tab + i * 16;
             const float4 w0 = *reinterpret_cast<const float4*>(row);
             const float4 w1 = *reinterpret_cast<const float4*>(row + 4);
@@ -571,7 +585,7 @@ __global__ void __launch_bounds__(256) k_interp_tl3(InterpArgs a, const int4* __
         // ---- output stage of the batch: one sample's CG coils per thread
         // (CG contiguous complex values of every [sample][coil] array,
         // 16-byte accesses)
-        for (int i = tid; i < nbt; i += 256) {
+        for (int i = tid; i < nbt; i += kTlThreads) {
             const int64_t s = start + b0 + i;
             const int64_t e = s * C + cg * CG;
             const float4* ob = reinterpret_cast<const float4*>(tab + i * 16);
@@ -644,7 +658,7 @@ size_t interp_tl3_lds_bytes(const int* B, int CG = kTlCG) {
 }
 
 bool interp_tl3_ok(int d, int W, const int* B, int C) {
-    return d == 3 && W == 4 && C % kTlCG == 0 && (B[0] + 3) * (B[1] + 3) * (B[2] + 3) * (kTlCG / 2) <= kTlStage * 256 &&
+    return d == 3 && W == 4 && C % kTlCG == 0 && (B[0] + 3) * (B[1] + 3) * (B[2] + 3) * (kTlCG / 2) <= kTlStage * kTlThreads &&
            interp_tl3_lds_bytes(B) <= 80 * 1024;
 }
 
@@ -690,9 +704,9 @@ void launch_interp_tiles(int d, int W, const InterpArgs& a, const int4* items, i
             (void)hipGetLastError();
         }
         if (b888)
-            hipLaunchKernelGGL((k_interp_tl3<8, 8, 8, kTlCG>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+            hipLaunchKernelGGL((k_interp_tl3<8, 8, 8, kTlCG>), dim3((unsigned)nb), dim3(kTlThreads), lds, s, a, items, kb);
         else
-            hipLaunchKernelGGL((k_interp_tl3<0, 0, 0, kTlCG>), dim3((unsigned)nb), dim3(256), lds, s, a, items, kb);
+            hipLaunchKernelGGL((k_interp_tl3<0, 0, 0, kTlCG>), dim3((unsigned)nb), dim3(kTlThreads), lds, s, a, items, kb);
         KP_LAUNCH_CHECK();
         return;
     }
@@ -1054,6 +1068,7 @@ __global__ void __launch_bounds__(256) k_spread_batch(const SpreadArgs* __restri
 void launch_spread_batch(const SpreadArgs* d_args, const int64_t* d_start, int n, int64_t nblk, int threads,
                          size_t lds, const KbParams& kb, hipStream_t s) {
     if (nblk <= 0) return;
+    if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "batched spreading grid too large");
     if (lds > 65536) {
         (void)hipFuncSetAttribute((const void*)k_spread_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();

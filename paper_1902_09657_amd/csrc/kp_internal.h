@@ -108,6 +108,16 @@ struct FftPass {
     const int2* xr;
     int xr_mode;
     int xr_G2C, xr_C, xr_B1, xr_B2, xr_nb2;
+    // and along axis 1: yr[tz] is the axis-1 cell range [lo, hi) holding every
+    // tile column (ty, tz) that has a non-empty spreading tile; grid rows
+    // (.., y, z, ..) with y outside the range of tz = z / B2 are zero in the
+    // adjoint and unused in the forward direction.  yr_mode 1: forward pass
+    // along axis 0, a column outside is not loaded (nothing of it is stored);
+    // 2: adjoint pass along axis 0, a column outside is not stored; 3:
+    // forward pass along axis 1, rows outside are not stored; 4: adjoint pass
+    // along axis 1, rows outside are not loaded and taken as zero
+    const int2* yr;
+    int yr_mode;
 };
 
 void launch_fft_pass(const FftPass& p, hipStream_t s);
@@ -119,10 +129,16 @@ size_t fft_lds_bytes(int L, int ncol);
 // ------------------------------------------------------------ gridding
 // Kaiser-Bessel weights of the W taps of a sample as polynomials in
 // x = frac(g) - 1/2: weight of tap t = sum_k poly[t][k] x^k (degree 9,
-// fitted on the host in double precision at Chebyshev nodes).
+// fitted on the host in double precision at Chebyshev nodes).  The kernel is
+// even, so tap W-1-t is tap t mirrored (x -> -x): with the even and odd
+// parts of tap t's polynomial as polynomials in x^2 (ev[t], od[t], degree 4),
+// tap t = ev + x od and tap W-1-t = ev - x od, for t < W/2.
 constexpr int kPolyN = 10;
+constexpr int kHalfN = kPolyN / 2;
 struct KbParams {
     float poly[8][kPolyN];
+    float ev[4][kHalfN];
+    float od[4][kHalfN];
 };
 void kb_fit(double beta, int W, KbParams* kb);
 double kb_kernel_host(double u, int W, double beta);
@@ -166,6 +182,7 @@ struct SpreadArgs {
 
 // spreading launch geometry derived from the tile shape
 constexpr int kSpreadChunk = 128;   // touch entries staged in LDS at a time
+constexpr bool kFftYPrune = true;        // y-range pruning of the 3D axis-0 / axis-1 FFT passes
 constexpr int kZMax = 8;            // tile extent along the last axis (max)
 int spread_threads(int d, const int* B, int C);
 int spread_nbk(int d, int W, const int* B);
@@ -214,6 +231,7 @@ struct Plan {
     DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
     DevBuf stouch, scode;         // touch entries in spreading order, their buckets
     DevBuf xrange;                // 3D: axis-0 cell range of the non-empty spreading tiles per (ty, tz)
+    DevBuf yrange;                // 3D: axis-1 cell range of the tile columns with a non-empty tile, per tz
     DevBuf partial;               // partial tiles of split tiles
     DevBuf iwork;                 // interpolation pieces (tile, start, count, 0)
     int64_t niwork = 0;
@@ -282,8 +300,11 @@ InterpArgs interp_args(Plan& P, const float2* grid, const InterpArgs& tmpl);
 // batched launches (fft.hip, grid.hip)
 bool fft_batchable(const FftPass& p);
 int64_t fft_pass_blocks(const FftPass& p);
-void launch_fft_batch(const FftPass* d_passes, const int64_t* d_blk_start, int n, int64_t nblk, int maxL, int nc,
-                      hipStream_t s);
+// one launch over the passes of a phase of mixed lengths (sorted by length);
+// map: the coil column block of the passes along the coils, else 0
+int fft_mixed_columns(int L, int nc_map);
+void launch_fft_batch_mixed(const FftPass* d_passes, const int64_t* d_blk_start, int n, int64_t nblk, int map,
+                            size_t lds, hipStream_t s);
 void launch_interp_batch(const InterpArgs* d_args, const int64_t* d_start, int n, int64_t nblk, const KbParams& kb,
                          hipStream_t s);
 void launch_spread_batch(const SpreadArgs* d_args, const int64_t* d_start, int n, int64_t nblk, int threads,

@@ -700,6 +700,23 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
             if (r.y <= r.x) r = make_int2(0, 0);
         P->xrange.alloc(sizeof(int2) * xr.size());
         KP_HIP(hipMemcpy(P->xrange.p, xr.data(), sizeof(int2) * xr.size(), hipMemcpyHostToDevice));
+        // per tz the axis-1 range of the tile columns that hold a non-empty
+        // tile (the columns outside it are empty: zero in the adjoint, unused
+        // in the forward direction)
+        std::vector<int2> yr((size_t)nb2, make_int2(0, 0));
+        for (int tz = 0; tz < nb2; ++tz) {
+            int lo = INT_MAX, hi = 0;
+            for (int ty = 0; ty < nb1; ++ty) {
+                const int2 r = xr[(size_t)ty * nb2 + tz];
+                if (r.y > r.x) {
+                    lo = std::min(lo, ty * P->Bs[1]);
+                    hi = std::max(hi, (ty + 1) * P->Bs[1]);
+                }
+            }
+            if (hi > lo) yr[(size_t)tz] = make_int2(lo, hi);
+        }
+        P->yrange.alloc(sizeof(int2) * yr.size());
+        KP_HIP(hipMemcpy(P->yrange.p, yr.data(), sizeof(int2) * yr.size(), hipMemcpyHostToDevice));
         // an empty tile inside its column's range is still written (zeros):
         // the first adjoint pass reads the whole range
         skip.assign((size_t)P->nstiles, 0);
@@ -874,7 +891,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_HIP(hipStreamSynchronize(s));
 
     int64_t total = 0;
-    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->xrange, &P->touch_off, &P->touch, &P->work,
+    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->xrange, &P->yrange, &P->touch_off, &P->touch, &P->work,
                       &P->heavy_list, &P->maps, &P->fo_fwd, &P->fr_fwd, &P->bufA, &P->bufB, &P->kint, &P->kint2, &P->kint3,
                       &P->pint, &P->red, &P->sched, &P->tvv, &P->kint4})
         total += (int64_t)b->bytes;
@@ -915,7 +932,8 @@ static void fill_stages(const Plan& P, int ax, FftPass& fp) {
 }
 
 // support pruning of an axis-0 pass over [G0][G1][G2][C] (mode 1: stores,
-// mode 2: loads)
+// mode 2: loads); the y-range pruning of the axis-0 and axis-1 passes
+// (yr_mode, see FftPass)
 static void set_xrange(const Plan& P, int C, int mode, FftPass& fp) {
     fp.xr = P.xrange.as<int2>();
     fp.xr_mode = mode;
@@ -924,6 +942,21 @@ static void set_xrange(const Plan& P, int C, int mode, FftPass& fp) {
     fp.xr_B1 = P.Bs[1];
     fp.xr_B2 = P.Bs[2];
     fp.xr_nb2 = P.nbs[2];
+}
+static void set_yrange(const Plan& P, int C, int mode, FftPass& fp) {
+    fp.yr = P.yrange.as<int2>();
+    fp.yr_mode = mode;
+    fp.xr_G2C = P.G[2] * C;
+    fp.xr_C = C;
+    fp.xr_B2 = P.Bs[2];
+}
+// the adjoint y-range pruning skips stores of the axis-0 pass that the axis-1
+// pass must then take as zero: both passes must run on the specialised kernel
+static bool yrange_ok(const Plan& P, int C) {
+    if (!P.yrange.p || !kFftYPrune) return false;
+    int Ob = 1, Ib = 1;
+    pass_blocking((int64_t)P.G[2] * C, &Ob, &Ib);  // the column block of the axis-1 passes
+    return fft_fixed_ok(P.G[0], 32) && fft_fixed_ok(P.G[1], Ob * Ib);
 }
 
 std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o) {
@@ -966,6 +999,7 @@ std::vector<FftPass> forward_passes(Plan& P, const float2* x, const FwdOpts& o) 
         }
         pass_blocking(I, &fp.Ob, &fp.Ib);
         if (ax == 0 && d == 3 && P.xrange.p) set_xrange(P, C, 1, fp);
+        if (d == 3 && (ax == 0 || ax == 1) && yrange_ok(P, C)) set_yrange(P, C, ax == 0 ? 1 : 3, fp);
         out.push_back(fp);
         prev = fp.out;
         which ^= 1;
@@ -1029,6 +1063,7 @@ std::vector<FftPass> adjoint_passes(Plan& P, float2* grid, float2* out, const Ad
             pass_blocking(I, &fp.Ob, &fp.Ib);
         }
         if (ax == 0 && d == 3 && P.xrange.p) set_xrange(P, C, 2, fp);
+        if (d == 3 && (ax == 0 || ax == 1) && yrange_ok(P, C)) set_yrange(P, C, ax == 0 ? 2 : 4, fp);
         res.push_back(fp);
         cur = dst;
     }

@@ -113,8 +113,8 @@ __global__ void __launch_bounds__(256) k_b_img(float2* gx, const float2* gxb, co
         gx[i] = make_float2(-th * b.x + gt.x / d, -th * b.y + gt.y / d);
         gahu[i] = make_float2(-t * gt.x / d, -t * gt.y / d);
     }
-    const double r0 = ublock_sum(s_th, sh), r1 = ublock_sum(s_tau, sh), r2 = ublock_sum(s_lam, sh);
-    if (threadIdx.x == 0) {
+    const double r0 = ublock_sum(s_tau, sh), r1 = ublock_sum(s_th, sh), r2 = ublock_sum(s_lam, sh);
+    if (threadIdx.x == 0) {  // in the order of the per-step sums: tau, theta, lambda
         part[blockIdx.x] = r0;
         part[kURed + blockIdx.x] = r1;
         part[2 * kURed + blockIdx.x] = r2;
@@ -238,35 +238,33 @@ void unrolled_forward(Plan& P, const void* y, const float* p, int p_kind, const 
     U.prm = prm;
     U.K = K;
     const int64_t N = L.N, MC = L.MC;
-    // running state in plan workspaces; step records in the segment area
-    float2* x = P.img[0].as<float2>();
-    float2* xb = P.img[1].as<float2>();
-    float2* u = P.kint.as<float2>();
-    float2* seg = B + L.seg;
-    float2* ax = seg;                 // scratch for the record of the current step
-    float2* u1 = seg + MC;
-    float2* ahu = seg + 2 * MC;
-    float2* x1 = seg + 2 * MC + N;
-    float2* xb1 = seg + 2 * MC + 2 * N;
+    // running state: two sets of (x, xbar, u) used in turn (plan workspaces
+    // and the segment area), so a step writes the other set and nothing is
+    // copied; ax and A^H u of the current step are scratch
+    float2* seg = B + L.seg;  // 2 MC + 3 N used of S (3 N + 3 MC)
+    float2* ax = seg;
+    float2* ahu = seg + MC;
+    float2* xs[2] = {P.img[0].as<float2>(), seg + MC + N};
+    float2* xbs[2] = {P.img[1].as<float2>(), seg + MC + 2 * N};
+    float2* us[2] = {P.kint.as<float2>(), seg + MC + 3 * N};
     if (x0)
-        copy2((const float2*)x0, x, N, s);
+        copy2((const float2*)x0, xs[0], N, s);
     else
-        fill2(x, N, 0.f, 0.f, s);
-    copy2(x, xb, N, s);
-    fill2(u, MC, 0.f, 0.f, s);
+        fill2(xs[0], N, 0.f, 0.f, s);
+    copy2(xs[0], xbs[0], N, s);
+    fill2(us[0], MC, 0.f, 0.f, s);
+    int cur = 0;
     for (int k = 0; k < K; ++k) {
         if (k % S == 0) {
             float2* c = B + L.ck + (int64_t)(k / S) * (2 * N + MC);
-            copy2(x, c, N, s);
-            copy2(xb, c + N, N, s);
-            copy2(u, c + 2 * N, MC, s);
+            copy2(xs[cur], c, N, s);
+            copy2(xbs[cur], c + N, N, s);
+            copy2(us[cur], c + 2 * N, MC, s);
         }
-        ustep(P, U, k, x, xb, u, ax, u1, ahu, x1, xb1, s);
-        copy2(x1, x, N, s);
-        copy2(xb1, xb, N, s);
-        copy2(u1, u, MC, s);
+        ustep(P, U, k, xs[cur], xbs[cur], us[cur], ax, us[cur ^ 1], ahu, xs[cur ^ 1], xbs[cur ^ 1], s);
+        cur ^= 1;
     }
-    copy2(x, (float2*)x_out, N, s);
+    copy2(xs[cur], (float2*)x_out, N, s);
 }
 
 void unrolled_backward(Plan& P, const void* y, const float* p, int p_kind, const float* prm, int K, int S,
@@ -303,32 +301,30 @@ void unrolled_backward(Plan& P, const void* y, const float* p, int p_kind, const
     fill2(gy, MC, 0.f, 0.f, s);
     for (int sg = L.nck - 1; sg >= 0; --sg) {
         const int k0 = sg * S, k1 = std::min(K, k0 + S);
-        // recompute the segment from its checkpoint
+        // recompute the segment from its checkpoint; step k reads x_k and
+        // u_k from the checkpoint (first step) or from the previous step's
+        // record, and xbar_k from one of two spare images used in turn
         const float2* c = B + L.ck + (int64_t)sg * (2 * N + MC);
         const float2* xk = c;
         const float2* xbk = c + N;
         const float2* uk = c + 2 * N;
+        float2* xbs[2] = {gxt, P.img[3].as<float2>()};
         for (int k = k0; k < k1; ++k) {
             float2* r = rec(k - k0);
-            float2* rx = r;              // x_k
-            float2* ru = r + N;          // u_k
             float2* rax = r + N + MC;    // ax_k
             float2* ru1 = r + N + 2 * MC;
             float2* rahu = r + N + 3 * MC;
             float2* rx1 = r + 2 * N + 3 * MC;
-            copy2(xk, rx, N, s);
-            copy2(uk, ru, MC, s);
-            ustep(P, U, k, rx, xbk, ru, rax, ru1, rahu, rx1, gxt, s);
-            // next step's inputs: x_{k+1}, xbar_{k+1} (kept in gxt / img[3]), u_{k+1}
-            copy2(gxt, P.img[3].as<float2>(), N, s);
+            float2* xb1 = xbs[(k - k0) & 1];
+            ustep(P, U, k, xk, xbk, uk, rax, ru1, rahu, rx1, xb1, s);
             xk = rx1;
-            xbk = P.img[3].as<float2>();
+            xbk = xb1;
             uk = ru1;
         }
         // reverse through the segment
         for (int k = k1 - 1; k >= k0; --k) {
             float2* r = rec(k - k0);
-            const float2* rx = r;
+            const float2* rx = k == k0 ? c : rec(k - 1 - k0) + 2 * N + 3 * MC;  // x_k
             const float2* rax = r + N + MC;
             const float2* ru1 = r + N + 2 * MC;
             const float2* rahu = r + N + 3 * MC;
@@ -336,10 +332,8 @@ void unrolled_backward(Plan& P, const void* y, const float* p, int p_kind, const
             hipLaunchKernelGGL(k_b_img, dim3(kURed), dim3(256), 0, s, gx, gxb, rx, rx1, rahu, prm + K + k,
                                prm + 2 * K + k, prm + 3 * K, N, gahu, part);
             KP_LAUNCH_CHECK();
-            // part[0] -> theta_k, part[1] -> tau_k, part[2] -> lambda_k
-            hipLaunchKernelGGL(k_u_final, dim3(1), dim3(256), 0, s, part, 1, st + 2 * K + k, 0);
-            hipLaunchKernelGGL(k_u_final, dim3(1), dim3(256), 0, s, part + kURed, 1, st + K + k, 0);
-            hipLaunchKernelGGL(k_u_final, dim3(1), dim3(256), 0, s, part + 2 * kURed, 1, st + 3 * K + k, 0);
+            // part[0] -> tau_k, part[1] -> theta_k, part[2] -> lambda_k (stride K)
+            hipLaunchKernelGGL(k_u_final, dim3(1), dim3(256), 0, s, part, 3, st + K + k, K);
             KP_LAUNCH_CHECK();
             apply_A(P, gahu, Ag, s);
             hipLaunchKernelGGL(k_b_k, dim3(kURed), dim3(256), 0, s, gu, Ag, rax, U.y, ru1, U.p, U.p_mc, C, prm + k, MC,

@@ -113,3 +113,42 @@ def test_schedule_params_match_solver():
     xs = kp.pdhg_solve(plan, yt, pt, reg="l2", lam=2e-3, iters=K, lambda_max=lmax)
     assert rel(xu.cpu().numpy(), xs.cpu().numpy()) < 1e-5
     plan.close()
+
+
+def test_unrolled_batch_equals_per_slice():
+    """UnrolledPdhgBatch (slices on concurrent side streams) gives the outputs
+    and gradients of UnrolledPdhg applied slice by slice, bit for bit (the
+    same kernels on the same data; the slices do not interact)."""
+    import paper_1902_09657_amd as kp
+    from paper_1902_09657_amd.autograd import schedule_params, unrolled_pdhg, unrolled_pdhg_batch
+    rng = np.random.default_rng(21)
+    plans, ys, ps, params, xts = [], [], [], [], []
+    for i, (shape, C, M) in enumerate([((32, 32), 4, 3000), ((40, 32), 4, 2500), ((32, 48), 4, 4000),
+                                       ((24, 24), 4, 1500), ((32, 32), 4, 2000)]):
+        k = synth.random_coords(M, 2, rng)
+        maps = synth.coil_maps(shape, C, rng)
+        x = synth.phantom(shape, rng)
+        op = onufft.Nufft(k, shape, maps, 1.25, 4)
+        y = op.forward(x) + synth.noise((C, M), 1e-3, rng)
+        plan = kp.nufft_plan(dev(k, torch.float32), shape, dev(maps, torch.complex64), oversamp=1.25, kb_width=4)
+        p = kp.precond_build(plan, kp.KP_PRECOND_MC if i % 2 == 0 else kp.KP_PRECOND_SC)
+        plans.append(plan)
+        ys.append(dev(y, torch.complex64))
+        ps.append(p)
+        params.append(schedule_params(plan, p, 6, lam=1e-2, lambda_max=1.5 + 0.1 * i))
+        xts.append(dev(x, torch.complex64))
+    print("unrolled batch of", len(plans), flush=True)
+    ths = [pr.clone().requires_grad_(True) for pr in params]
+    yb = [y.clone().requires_grad_(True) for y in ys]
+    xb = unrolled_pdhg_batch(yb, ths, plans, ps, 6, ckpt_every=2)
+    loss = sum(0.5 * ((x - t).abs() ** 2).sum() for x, t in zip(xb, xts))
+    loss.backward()
+    for i, plan in enumerate(plans):
+        th = params[i].clone().requires_grad_(True)
+        yi = ys[i].clone().requires_grad_(True)
+        xi = unrolled_pdhg(yi, th, plan, ps[i], 6, ckpt_every=2)
+        (0.5 * ((xi - xts[i]).abs() ** 2).sum()).backward()
+        assert torch.equal(xi.detach(), xb[i].detach())
+        assert torch.equal(th.grad, ths[i].grad)
+        assert torch.equal(yi.grad, yb[i].grad)
+        plan.close()
