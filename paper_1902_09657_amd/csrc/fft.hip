@@ -14,6 +14,7 @@
 // adjoint pass fuses the mirror post-pass (conj(s_c), deapodisation, sign,
 // coil sum) and, optionally, the PDHG primal update.
 #include <algorithm>
+#include <type_traits>
 
 #include "kp_internal.h"
 
@@ -326,13 +327,14 @@ __device__ __forceinline__ void fixed_stage(float2* buf, const float2* __restric
         const int j = tid / NC + k * (NT / NC);
         if (k * NT + tid < TOT) {
             const int kk = j % NS;
-            if (NS > 1) {
+            if (NS > 1) {  // one table read; the other twiddles as its powers
+                float2 w[R];
+                w[1] = tw[kk * STRIDE];
+                if (inv) w[1].y = -w[1].y;
 #pragma unroll
-                for (int t = 1; t < R; ++t) {
-                    float2 w = tw[t * kk * STRIDE];
-                    if (inv) w.y = -w.y;
-                    v[k][t] = cmul(v[k][t], w);
-                }
+                for (int t = 2; t < R; ++t) w[t] = cmul(w[t >> 1], w[t - (t >> 1)]);
+#pragma unroll
+                for (int t = 1; t < R; ++t) v[k][t] = cmul(v[k][t], w[t]);
             }
             dft_c<R>(v[k], inv);
             const int base = (j / NS) * NS * R + kk;
@@ -523,6 +525,238 @@ __global__ void __launch_bounds__(NT) k_fft_fixed(FftPass p) {
     fft_fixed_body<L, NC, NT>(p, blockIdx.x, buf);
 }
 
+// ------------------------------------------------------------------------
+// Register-resident two-factor pass for plain lines (no fused pre- or
+// post-pass): L = N1 x N2 with n = N2 n1 + n2 and k = k1 + N1 k2,
+//   X[k1 + N1 k2] = sum_n2 W_N2^(n2 k2) [ W_L^(n2 k1) sum_n1 x[N2 n1 + n2] W_N1^(n1 k1) ].
+// Step 1: one thread per (n2, column) takes its N1 inputs straight from
+// global memory, does the N1-point DFT and the twiddle W_L^(n2 k1) in
+// registers and writes the N1 results to LDS.  Step 2: one thread per
+// (k1, column) reads its N2 values back and does the N2-point DFT in
+// registers (its twiddles are compile-time constants), then stores the N2
+// outputs straight to global memory.  One LDS round trip and one barrier per
+// pass instead of one per radix stage; the only table read is W_L^n2, whose
+// powers W_L^(n2 k1) are formed by complex products.
+
+// cos and sin of 2 pi m / n (m >= 0) at compile time: quadrant reduction,
+// then Taylor series on [0, pi/2) (terms to x^27: far below double rounding)
+constexpr double kc_taylor_sin(double x) {
+    double t = x, s = x;
+    for (int k = 1; k < 14; ++k) {
+        t *= -x * x / (double)((2 * k) * (2 * k + 1));
+        s += t;
+    }
+    return s;
+}
+constexpr double kc_taylor_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        t *= -x * x / (double)((2 * k - 1) * (2 * k));
+        s += t;
+    }
+    return s;
+}
+constexpr double kc_phase(int m, int n, int* quad) {
+    const int r = m % n, q = (4 * r) / n;
+    *quad = q;
+    return 3.14159265358979323846 * (double)(4 * r - q * n) / (2.0 * (double)n);
+}
+constexpr double kc_cos(int m, int n) {
+    int q = 0;
+    const double ph = kc_phase(m, n, &q);
+    const double c = kc_taylor_cos(ph), s = kc_taylor_sin(ph);
+    return q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+constexpr double kc_sin(int m, int n) {
+    int q = 0;
+    const double ph = kc_phase(m, n, &q);
+    const double c = kc_taylor_cos(ph), s = kc_taylor_sin(ph);
+    return q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+}
+
+// compile-time loop: f(integral_constant<int, I>) for I = B .. E - 1
+template <int B, int E>
+struct Unroll {
+    template <typename F>
+    __device__ __forceinline__ static void run(F& f) {
+        if constexpr (B < E) {
+            f(std::integral_constant<int, B>());
+            Unroll<B + 1, E>::run(f);
+        }
+    }
+};
+
+// in-place N-point DFT of v (sign by INV) in registers: N = R x M split as
+// above, recursively, down to the radix kernels
+template <int N, int INV>
+__device__ __forceinline__ void dft_reg(float2* v) {
+    if constexpr (N == 2 || N == 3 || N == 4 || N == 5 || N == 8) {
+        dft_c<N>(v, INV);
+    } else {
+        constexpr int R = fft_radix_c(N, 0), M = N / R;
+        float2 y[N];
+        auto col = [&](auto n2c) {
+            constexpr int n2 = decltype(n2c)::value;
+            float2 t[R];
+#pragma unroll
+            for (int n1 = 0; n1 < R; ++n1) t[n1] = v[M * n1 + n2];
+            dft_c<R>(t, INV);
+            y[n2] = t[0];
+            auto tw = [&](auto k1c) {
+                constexpr int k1 = decltype(k1c)::value;
+                constexpr float wr = (float)kc_cos(n2 * k1, N);
+                constexpr float wi = (float)((INV ? 1.0 : -1.0) * kc_sin(n2 * k1, N));
+                y[k1 * M + n2] = n2 == 0 ? t[k1] : cmul(t[k1], make_float2(wr, wi));
+            };
+            Unroll<1, R>::run(tw);
+        };
+        Unroll<0, M>::run(col);
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) dft_reg<M, INV>(y + k1 * M);
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < M; ++k2) v[k1 + R * k2] = y[k1 * M + k2];
+    }
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;     // buffer resource word 3 (raw dword access)
+constexpr uint32_t kBufOff = 0x80000000u;  // an offset past every record count used here
+
+template <int L, int N1, int NC, int INV>
+__device__ __forceinline__ void fft_reg_body(const FftPass& p, int64_t bid, float2* buf) {
+    constexpr int N2 = L / N1;
+    constexpr int NT = N1 * NC;
+    constexpr int LS = NC + 1;                    // LDS row stride (padded)
+    constexpr int NJ = (N2 * NC + NT - 1) / NT;   // step-1 tasks per thread
+    static_assert(N1 * N2 == L, "L = N1 N2");
+    const int tid = threadIdx.x;
+    const int col = tid % NC, tr = tid / NC;      // tr < N1
+    const int64_t nIb = (p.I + p.Ib - 1) / p.Ib;
+    const int64_t o0 = (bid / nIb) * p.Ob;
+    const int64_t i0 = (bid % nIb) * p.Ib;
+    const int64_t o = o0 + col / p.Ib, i = i0 + col % p.Ib;
+    const bool live = o < p.O && i < p.I;
+    // support pruning, per column, as in the LDS-staged pass
+    int xlo = 0, xhi = L;
+    if (p.xr_mode && live) {
+        const int64_t yy = i / p.xr_G2C;
+        const int zz = (int)((i % p.xr_G2C) / p.xr_C);
+        const int2 r = p.xr[(yy / p.xr_B1) * p.xr_nb2 + zz / p.xr_B2];
+        xlo = r.x;
+        xhi = r.y;
+    }
+    int ylo = 0, yhi = L;
+    bool col_out = false;
+    if (p.yr_mode && live) {
+        const int zz = (int)((i % p.xr_G2C) / p.xr_C);
+        const int2 r = p.yr[zz / p.xr_B2];
+        if (p.yr_mode <= 2) {
+            const int64_t yy = i / p.xr_G2C;
+            col_out = !(yy >= r.x && yy < r.y);
+        } else {
+            ylo = r.x;
+            yhi = r.y;
+        }
+    }
+
+    // ---- step 1: loads of every task of this thread first, then the DFTs.
+    // Loads and stores are buffer accesses relative to the block's first
+    // element: a lane whose value is zero (padding, a pruned row, a dead
+    // column, a missing task) or whose row is not stored gets the offset
+    // kBufOff, past the record count, which the hardware answers with zero
+    // (load) or drops (store) without a memory access, so no access needs a
+    // branch.  The host keeps every valid byte offset of the pass below 2^31.
+    const __amdgpu_buffer_rsrc_t rin =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(p.in + o0 * p.in_os + i0), (short)0, 0x7fffffff, kBufWord3);
+    const uint32_t colb = (uint32_t)(((o - o0) * p.in_os + (i - i0)) * 8);
+    const uint32_t rsb = (uint32_t)(p.in_rs * 8);
+    int lo = 0, hi = p.Lin;  // input rows taken from memory; the others are zero
+    if (p.xr_mode == 2) {
+        lo = xlo;
+        hi = min(xhi, p.Lin);
+    } else if (p.yr_mode == 4) {
+        lo = ylo;
+        hi = min(yhi, p.Lin);
+    }
+    if (!live || (p.yr_mode == 1 && col_out)) hi = lo;
+    const int half = p.Lin / 2;
+    const int zlo = p.pad_in ? p.Lin - half : p.Lin, zhi = p.pad_in ? L - half : L;  // zero positions
+    float2 v[NJ][N1];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int n2 = tr + j * N1;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int pos = N2 * n1 + n2;
+            const int r = pos >= zhi ? pos - zhi : pos + (p.pad_in ? half : 0);  // input row at this position
+            const bool ok = (n2 < N2) & ((pos < zlo) | (pos >= zhi)) & (r >= lo) & (r < hi);
+            const uint32_t off = ok ? colb + (uint32_t)r * rsb : kBufOff;
+            const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rin, off, 0, 0);
+            v[j][n1] = make_float2(__uint_as_float(t.x), __uint_as_float(t.y));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int n2 = tr + j * N1;
+        if (n2 < N2) {
+            dft_reg<N1, INV>(v[j]);
+            float2 w[N1];
+            w[0] = make_float2(1.f, 0.f);
+            w[1] = p.tw[n2];
+            if (INV) w[1].y = -w[1].y;
+#pragma unroll
+            for (int k1 = 2; k1 < N1; ++k1) w[k1] = cmul(w[k1 >> 1], w[k1 - (k1 >> 1)]);
+            buf[n2 * LS + col] = v[j][0];
+#pragma unroll
+            for (int k1 = 1; k1 < N1; ++k1) buf[(k1 * N2 + n2) * LS + col] = cmul(v[j][k1], w[k1]);
+        }
+    }
+    __syncthreads();
+
+    // ---- step 2: thread (k1 = tr, col)
+    float2 y[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) y[n2] = buf[(tr * N2 + n2) * LS + col];
+    dft_reg<N2, INV>(y);
+    const __amdgpu_buffer_rsrc_t rout =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(p.out + o0 * p.out_os + i0), (short)0, 0x7fffffff, kBufWord3);
+    const uint32_t colo = (uint32_t)(((o - o0) * p.out_os + (i - i0)) * 8);
+    const uint32_t rso = (uint32_t)(p.out_rs * 8);
+    // rows stored: [slo, shi) of the pruning range, none for a dead or empty column
+    int slo = 0, shi = p.Lout;
+    if (p.xr_mode == 1) {
+        slo = xlo;
+        shi = min(xhi, p.Lout);
+    } else if (p.yr_mode == 3) {
+        slo = ylo;
+        shi = min(yhi, p.Lout);
+    }
+    if (!live || (p.yr_mode == 2 && col_out)) shi = slo;
+    const int cshift = p.crop_out ? p.Lout / 2 : 0;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+        const int q = tr + N1 * k2;
+        int m = q + cshift;  // output row of transform index q (centred crop)
+        m -= m >= L ? L : 0;
+        const uint32_t off = ((m >= slo) & (m < shi)) ? colo + (uint32_t)m * rso : kBufOff;
+        u32x2 t;
+        t.x = __float_as_uint(y[k2].x);
+        t.y = __float_as_uint(y[k2].y);
+        __builtin_amdgcn_raw_buffer_store_b64(t, rout, off, 0, 0);
+    }
+}
+
+template <int L, int N1, int NC>
+__global__ void __launch_bounds__(N1 * NC) k_fft_reg(FftPass p) {
+    extern __shared__ float2 buf[];
+    if (p.inverse)
+        fft_reg_body<L, N1, NC, 1>(p, blockIdx.x, buf);
+    else
+        fft_reg_body<L, N1, NC, 0>(p, blockIdx.x, buf);
+}
+
 // Column blocks of the specialised kernels: NC columns over NT threads with
 // NT a multiple of NC (8, 16 or 32 columns on 256 threads; 12 columns, one
 // 12-coil row, on 384 threads: 8-10 % faster than 192 on the 2D 12-coil
@@ -637,9 +871,51 @@ static fft_kernel_t fixed_for(int L) {
     }
 }
 
-// try the specialised kernel; false if this pass does not fit it
+// register-resident passes: plain 32-column passes of lengths 8 x N2 with an
+// N2-point DFT small enough for registers
+// register-resident passes: plain 32-column passes of lengths 8 x N2 with an
+// N2-point DFT small enough for registers.  The fused map passes stay on the
+// LDS-staged kernel: 25 values per lane cap a register pass at about 11
+// waves per CU, and those passes ran slower in that form.
+static fft_kernel_t reg_for(const FftPass& p) {
+    if (p.pre != PRE_NONE || p.post != POST_NONE || p.Ob * p.Ib != 32) return nullptr;
+    switch (p.L) {
+        case 160: return k_fft_reg<160, 8, 32>;
+        case 200: return k_fft_reg<200, 8, 32>;
+        case 240: return k_fft_reg<240, 8, 32>;
+        case 256: return k_fft_reg<256, 8, 32>;
+        default: return nullptr;
+    }
+}
+
+// the register-resident pass addresses a block's input and output through
+// 32-bit byte offsets below 2^31
+static bool reg_span_ok(const FftPass& p) {
+    const int64_t lim = 0x7ffffff0;
+    const int64_t in_span = ((int64_t)(p.Ob - 1) * p.in_os + (p.Ib - 1) + (int64_t)(p.Lin - 1) * p.in_rs + 1) * 8;
+    const int64_t out_span = ((int64_t)(p.Ob - 1) * p.out_os + (p.Ib - 1) + (int64_t)(p.Lout - 1) * p.out_rs + 1) * 8;
+    return p.in_os >= 0 && p.in_rs >= 0 && p.out_os >= 0 && p.out_rs >= 0 && in_span < lim && out_span < lim;
+}
+
+// try the specialised kernels; false if this pass fits neither
 static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     const int nc = p.Ob * p.Ib;
+    fft_kernel_t fr = reg_for(p);
+    if (fr && reg_span_ok(p)) {
+        const size_t lds = sizeof(float2) * (size_t)p.L * 33;
+        if (lds <= (size_t)lim) {
+            if (lds > 65536) {
+                (void)hipFuncSetAttribute((const void*)fr, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+                (void)hipGetLastError();
+            }
+            const int64_t nblk = fft_pass_blocks(p);
+            if (nblk <= 0) return true;
+            if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "FFT pass grid too large");
+            hipLaunchKernelGGL(fr, dim3((unsigned)nblk), dim3(8 * 32), lds, s, p);
+            KP_LAUNCH_CHECK();
+            return true;
+        }
+    }
     const int nt = fixed_threads(nc);
     if (nt == 0) return false;
     if (p.post == POST_MAPS && (nt % p.Ob) != 0) return false;

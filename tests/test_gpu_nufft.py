@@ -54,6 +54,14 @@ CASES = [
     ((160, 128), 8, 20000, 1.25, 4),
     ((128, 200), 1, 20000, 2.0, 4),
     ((128, 128, 160), 2, 30000, 1.25, 4),
+    # register-resident passes along axes 0 and 1 (lengths 200, 240, 256)
+    ((24, 160, 24), 2, 8000, 1.25, 4),
+    ((192, 24, 24), 2, 8000, 1.25, 4),
+    ((128, 24, 40), 2, 8000, 2.0, 4),
+    # and along the coil-map axis (fused coil multiply / coil sum), C = 8, 4, 1
+    ((16, 16, 128), 8, 4000, 1.25, 4),
+    ((16, 24, 192), 4, 4000, 1.25, 4),
+    ((24, 16, 160), 1, 3000, 1.25, 4),
     # 3D, coils in groups of four (the tap-lane interpolation)
     ((24, 32, 40), 4, 6000, 1.25, 4),
     ((40, 36, 44), 8, 30000, 1.25, 4),

@@ -125,6 +125,10 @@ SOLVE_CASES = [
     ((40, 24, 16), 2, 4000, 1.25, 4, "l1wav", 5e-3, "mc", 8, 3),
     # deepest level two samples long on axis 0 (one coefficient per band)
     ((8, 16, 16), 2, 2000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 3),
+    # the last axis on a register-resident FFT length (160): the primal
+    # updates fused into its coil-sum pass
+    ((16, 16, 128), 4, 4000, 1.25, 4, "l2", 1e-3, "mc", 8, 2),
+    ((16, 16, 128), 8, 4000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 2),
 ]
 
 
