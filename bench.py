@@ -610,8 +610,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and differentiable forms")
     ap.add_argument("--profile-stages", type=int, default=0, metavar="R",
-                    help="counter-collection mode: build the plan, run each NUFFT stage R times and a plain copy of "
-                         "512 MiB (read) + 512 MiB (write) for calibration, then exit without a JSON line")
+                    help="counter-collection mode: build the plan, run the wavelet prox and each NUFFT stage R "
+                         "times and a plain copy of 512 MiB (read) + 512 MiB (write) for calibration, then exit "
+                         "without a JSON line")
     ap.add_argument("--form-only", choices=["batched", "differentiable"], default=None,
                     help="profiling mode: run only that form's measurement and print its JSON object (no headline "
                          "line)")
@@ -659,7 +660,8 @@ def main():
         plan = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
         L = _lib.load()
         sp = ctypes_stream(torch.cuda.current_stream())
-        for st in (_lib.KP_STAGE_FWD_FFT, _lib.KP_STAGE_INTERP, _lib.KP_STAGE_SPREAD, _lib.KP_STAGE_ADJ_FFT):
+        for st in (_lib.KP_STAGE_PROX, _lib.KP_STAGE_FWD_FFT, _lib.KP_STAGE_INTERP, _lib.KP_STAGE_SPREAD,
+                   _lib.KP_STAGE_ADJ_FFT):
             _lib.check(L.nufft_stage(plan.handle, st, args.profile_stages, sp))
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -769,7 +771,8 @@ def main():
     sp = ctypes_stream(s)
     stage_ms = {}
     for name, st in [("fwd_fft", _lib.KP_STAGE_FWD_FFT), ("interp", _lib.KP_STAGE_INTERP),
-                     ("spread", _lib.KP_STAGE_SPREAD), ("adj_fft", _lib.KP_STAGE_ADJ_FFT)]:
+                     ("spread", _lib.KP_STAGE_SPREAD), ("adj_fft", _lib.KP_STAGE_ADJ_FFT),
+                     ("wavelet_prox", _lib.KP_STAGE_PROX)]:
         _lib.check(L.nufft_stage(plan.handle, st, 2, sp))
         torch.cuda.synchronize()
         e0.record(s)

@@ -264,9 +264,15 @@ int nufft_plan_validate(int ndim, const int64_t* shape, int64_t ncoils, int64_t 
  *   KP_STAGE_SPREAD   tile spreading of internal k-space onto the grid
  *   KP_STAGE_ADJ_FFT  pruned inverse FFT passes + post-pass (d kernels)
  *   KP_STAGE_SPREAD_TILES  the tile kernel of KP_STAGE_SPREAD alone (split
- *                     tiles left as unreduced partial tiles) */
+ *                     tiles left as unreduced partial tiles)
+ *   KP_STAGE_PROX     one l1-db4 proximal step of the PDHG primal update
+ *                     (Preconditioned PDHG for simple regularizers, with the
+ *                     l1-wavelet term: analysis, soft threshold,
+ *                     synthesis, x and xbar update) on the plan's
+ *                     image workspaces, with as many levels up to 4 as every
+ *                     image extent allows (extents are even: at least one) */
 enum { KP_STAGE_FWD_FFT = 0, KP_STAGE_INTERP = 1, KP_STAGE_SPREAD = 2, KP_STAGE_ADJ_FFT = 3,
-       KP_STAGE_SPREAD_TILES = 4 };
+       KP_STAGE_SPREAD_TILES = 4, KP_STAGE_PROX = 5 };
 int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream);
 
 /* ---------------------------------------------------------------- batches

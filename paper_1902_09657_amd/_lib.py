@@ -29,7 +29,7 @@ EXPORTS = [
     "kp_db4_filter", "nufft_plan_validate", "kp_last_error", "nufft_stage",
     "pdhg_schedule_params", "l2_dual_cg", "nufft_autotune", "nufft_plan_batch", "nufft_batch_info", "pdhg_solve_batch", "nufft_batch_destroy",
 ]
-KP_STAGE_FWD_FFT, KP_STAGE_INTERP, KP_STAGE_SPREAD, KP_STAGE_ADJ_FFT, KP_STAGE_SPREAD_TILES = 0, 1, 2, 3, 4
+KP_STAGE_FWD_FFT, KP_STAGE_INTERP, KP_STAGE_SPREAD, KP_STAGE_ADJ_FFT, KP_STAGE_SPREAD_TILES, KP_STAGE_PROX = 0, 1, 2, 3, 4, 5
 
 
 class KpError(RuntimeError):

@@ -343,6 +343,7 @@ void dwt(float2* x, const int64_t* N, int d, int levels, bool inverse, hipStream
 void power_method(Plan& P, const float* pint, int p_mc, int iters, float* lam_out, hipStream_t s);
 const float* load_p(Plan& P, const float* p, int p_kind, hipStream_t s);
 void upload_wavelet_constants();
+void wavelet_prox_stage(Plan& P, hipStream_t s);
 void fft_twiddles(int L, DevBuf& tw);
 void pass_blocking(int64_t I, int* Ob, int* Ib);
 std::vector<double> db4_filter_host();

@@ -1287,7 +1287,7 @@ int nufft_plan_grid_coords(kp_plan_t plan, float* g, void* stream) {
 int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
-        if (stage < 0 || stage > 4) fail(KP_ERR_INVALID_ARG, "unknown stage");
+        if (stage < 0 || stage > KP_STAGE_PROX) fail(KP_ERR_INVALID_ARG, "unknown stage");
         if (reps < 1) fail(KP_ERR_INVALID_ARG, "reps must be >= 1");
         Plan& P = *plan->impl;
         hipStream_t s = (hipStream_t)stream;
@@ -1304,6 +1304,8 @@ int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream) {
                 spread_to_grid(P, P.kint.as<float2>(), (int)P.C, s);
             } else if (stage == KP_STAGE_SPREAD_TILES) {
                 launch_spread(P.d, P.W, spread_args(P, P.kint.as<float2>(), (int)P.C), P.kb, s);
+            } else if (stage == KP_STAGE_PROX) {
+                wavelet_prox_stage(P, s);
             } else {
                 AdjOpts ao;
                 grid_to_image(P, P.bufA.as<float2>(), P.img[3].as<float2>(), ao, s);

@@ -509,25 +509,31 @@ __device__ __forceinline__ void dwt3_brick(const Dwt3Args& a, int* q) {
     q[0] = r / a.nb[1];
 }
 
-// Brick load: the (2B + 6)^3 input values into LDS, every load of the thread
-// issued before the first LDS write.  pos(axis, u) gives the element index
-// along an axis of brick row u.
+// Brick load: the (2B + 6)^3 input values into LDS.  Thread t < IN^2 owns
+// the column (u1, u2) = (t / IN, t % IN) of the brick and loads its IN values
+// along axis 0: its axis-1/2 offset is computed once, the axis-0 offsets are
+// the same for the whole block (scalar), and every load of the thread is
+// issued before its first LDS write.  pos(axis, u) gives the element index
+// along an axis of brick row u; the products are 24-bit (N1 N2 < 2^24 is
+// checked on the host).  LDS rows along axis 2 are padded to IN + 1
+// elements: the axis-2 pass reads one row per lane, and rows of an odd
+// number of 8-byte elements put 16 consecutive lanes on 16 different bank
+// pairs (with IN = 14, lanes 8 apart shared banks).
+template <int IN>
+__host__ __device__ constexpr int dwt3_row() { return IN + 1; }
 template <int IN, typename Pos>
 __device__ __forceinline__ void dwt3_load(const Dwt3Args& a, float2* buf, Pos pos) {
-    constexpr int NLD = (IN * IN * IN + 255) / 256;
+    constexpr int P2 = dwt3_row<IN>();
     const int tid = threadIdx.x;
-    float2 v[NLD];
+    if (tid < IN * IN) {
+        const int u1 = tid / IN, u2 = tid - u1 * IN;
+        const float2* src = a.in + __umul24(pos(1, u1), a.S1) + pos(2, u2);
+        float2 v[IN];
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-        const int i = tid + k * 256;
-        if (i < IN * IN * IN) {
-            const int u2 = i % IN, u1 = (i / IN) % IN, u0 = i / (IN * IN);
-            v[k] = a.in[pos(0, u0) * a.S0 + pos(1, u1) * a.S1 + pos(2, u2)];
-        }
+        for (int u0 = 0; u0 < IN; ++u0) v[u0] = src[__umul24(pos(0, u0), a.S0)];
+#pragma unroll
+        for (int u0 = 0; u0 < IN; ++u0) buf[(u0 * IN + u1) * P2 + u2] = v[u0];
     }
-#pragma unroll
-    for (int k = 0; k < NLD; ++k)
-        if (tid + k * 256 < IN * IN * IN) buf[tid + k * 256] = v[k];
 }
 
 // analysis of one line held in registers: outputs r < B low band, r >= B high
@@ -571,22 +577,28 @@ __device__ __forceinline__ void dwt3_inv_line(const float2* v, float2* o) {
 template <int B>
 __global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
     constexpr int IN = 2 * B + 6, OB = 2 * B;
-    extern __shared__ float2 buf[];  // [IN][IN][IN]
+    extern __shared__ float2 buf[];  // [IN][IN][IN + 1]
     int q[3];
     dwt3_brick(a, q);
     const int tid = threadIdx.x;
     const float tsoft = *a.tau * a.lam;
     const int h0 = a.n[0] / 2, h1 = a.n[1] / 2, h2 = a.n[2] / 2;
-    // input rows 2 k0 .. 2 k0 + 2B + 5 of every axis, periodic
+    // input rows 2 k0 .. 2 k0 + 2B + 5 of every axis, periodic: one wrap
+    // needs one subtraction when the extent is at least IN, a loop otherwise
+    // (deep levels of small images)
     dwt3_load<IN>(a, buf, [&](int ax, int u) {
+        const int n = a.n[ax];
         int sidx = 2 * q[ax] * B + u;
-        if (sidx >= a.n[ax]) sidx %= a.n[ax];
+        sidx -= sidx >= n ? n : 0;
+        if (n < IN)
+            while (sidx >= n) sidx -= n;
         return sidx;
     });
     __syncthreads();
+    constexpr int P2 = dwt3_row<IN>();
     float2 v[IN], o[OB];
     if (tid < IN * IN) {  // axis 2: line (i0, i1)
-        float2* line = buf + tid * IN;
+        float2* line = buf + tid * P2;
 #pragma unroll
         for (int j = 0; j < IN; ++j) v[j] = line[j];
         dwt3_fwd_line<B, IN>(v, o);
@@ -595,24 +607,24 @@ __global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
     }
     __syncthreads();
     if (tid < IN * OB) {  // axis 1: line (i0, r2)
-        float2* line = buf + (tid / OB) * IN * IN + tid % OB;
+        float2* line = buf + (tid / OB) * IN * P2 + tid % OB;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * IN];
+        for (int j = 0; j < IN; ++j) v[j] = line[j * P2];
         dwt3_fwd_line<B, IN>(v, o);
 #pragma unroll
-        for (int r = 0; r < OB; ++r) line[r * IN] = o[r];
+        for (int r = 0; r < OB; ++r) line[r * P2] = o[r];
     }
     __syncthreads();
     if (tid < OB * OB) {  // axis 0: line (r1, r2), soft threshold, store
         const int r1 = tid / OB, r2 = tid % OB;
-        const float2* line = buf + r1 * IN + r2;
+        const float2* line = buf + r1 * P2 + r2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * IN];
+        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * P2];
         dwt3_fwd_line<B, IN>(v, o);
         const int c1 = q[1] * B + (r1 < B ? r1 : r1 - B);
         const int c2 = q[2] * B + (r2 < B ? r2 : r2 - B);
         if (c1 >= h1 || c2 >= h2) return;  // past the block (last brick of an axis)
-        const int p12 = (r1 < B ? c1 : h1 + c1) * a.S1 + (r2 < B ? c2 : h2 + c2);
+        const int p12 = __umul24(r1 < B ? c1 : h1 + c1, a.S1) + (r2 < B ? c2 : h2 + c2);
 #pragma unroll
         for (int r0 = 0; r0 < OB; ++r0) {
             const int c0 = q[0] * B + (r0 < B ? r0 : r0 - B);
@@ -623,7 +635,7 @@ __global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
                 const float g = m2 > tsoft * tsoft ? 1.f - tsoft * rsqrtf(m2) : 0.f;
                 acc = make_float2(acc.x * g, acc.y * g);
             }
-            a.out[(r0 < B ? c0 : h0 + c0) * a.S0 + p12] = acc;
+            a.out[__umul24(r0 < B ? c0 : h0 + c0, a.S0) + p12] = acc;
         }
     }
 }
@@ -633,22 +645,44 @@ __global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
 template <int B, int FUSE>
 __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
     constexpr int NB = B + 3, IN = 2 * NB, OB = 2 * B;
-    extern __shared__ float2 buf[];  // [IN][IN][IN] (per axis: low band u < NB, high band NB + u)
+    extern __shared__ float2 buf[];  // [IN][IN][IN + 1] (per axis: low band u < NB, high band NB + u)
     int q[3];
     dwt3_brick(a, q);
     const int tid = threadIdx.x;
     const float th = FUSE == 2 ? *a.theta : 0.f;
     const int hh[3] = {a.n[0] / 2, a.n[1] / 2, a.n[2] / 2};
+    // x_old of the line a last-pass thread will write, loaded first so that
+    // its latency hides behind the brick load and the first two passes
+    float2 xo[OB];
+    const int m1 = tid / OB, m2 = tid % OB;
+    const int g1 = 2 * q[1] * B + m1, g2 = 2 * q[2] * B + m2;
+    const bool tail = tid < OB * OB && g1 < a.n[1] && g2 < a.n[2];
+    const int e12 = __umul24(g1, a.S1) + g2;
+    if (FUSE == 2 && tail) {
+#pragma unroll
+        for (int m0 = 0; m0 < OB; ++m0) {
+            const int g0 = min(2 * q[0] * B + m0, a.n[0] - 1);
+            xo[m0] = a.ex[__umul24(g0, a.S0) + e12];
+        }
+    }
+    // coefficient k0 - 3 + u of each band, periodic in [0, h): one
+    // correction each way when h >= NB, a loop otherwise
     dwt3_load<IN>(a, buf, [&](int ax, int u) {
         const int h = hh[ax];
         int kk = q[ax] * B - 3 + (u >= NB ? u - NB : u);
-        if (kk < 0 || kk >= h) kk = ((kk % h) + h) % h;
+        kk += kk < 0 ? h : 0;
+        kk -= kk >= h ? h : 0;
+        if (h < NB) {
+            while (kk < 0) kk += h;
+            while (kk >= h) kk -= h;
+        }
         return (u >= NB ? h : 0) + kk;
     });
     __syncthreads();
+    constexpr int P2 = dwt3_row<IN>();
     float2 v[IN], o[OB];
     if (tid < IN * IN) {
-        float2* line = buf + tid * IN;
+        float2* line = buf + tid * P2;
 #pragma unroll
         for (int j = 0; j < IN; ++j) v[j] = line[j];
         dwt3_inv_line<B>(v, o);
@@ -657,36 +691,24 @@ __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
     }
     __syncthreads();
     if (tid < IN * OB) {
-        float2* line = buf + (tid / OB) * IN * IN + tid % OB;
+        float2* line = buf + (tid / OB) * IN * P2 + tid % OB;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * IN];
+        for (int j = 0; j < IN; ++j) v[j] = line[j * P2];
         dwt3_inv_line<B>(v, o);
 #pragma unroll
-        for (int m = 0; m < OB; ++m) line[m * IN] = o[m];
+        for (int m = 0; m < OB; ++m) line[m * P2] = o[m];
     }
     __syncthreads();
-    if (tid < OB * OB) {
-        const int m1 = tid / OB, m2 = tid % OB;
-        const float2* line = buf + m1 * IN + m2;
+    if (tail) {
+        const float2* line = buf + m1 * P2 + m2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * IN];
-        const int g1 = 2 * q[1] * B + m1, g2 = 2 * q[2] * B + m2;
-        if (g1 >= a.n[1] || g2 >= a.n[2]) return;
-        const int e12 = g1 * a.S1 + g2;
-        float2 xo[OB];
-        if (FUSE == 2) {  // x_old of the line, loaded before the filtering
-#pragma unroll
-            for (int m0 = 0; m0 < OB; ++m0) {
-                const int g0 = min(2 * q[0] * B + m0, a.n[0] - 1);
-                xo[m0] = a.ex[g0 * a.S0 + e12];
-            }
-        }
+        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * P2];
         dwt3_inv_line<B>(v, o);
 #pragma unroll
         for (int m0 = 0; m0 < OB; ++m0) {
             const int g0 = 2 * q[0] * B + m0;
             if (g0 >= a.n[0]) continue;
-            const int e = g0 * a.S0 + e12;
+            const int e = __umul24(g0, a.S0) + e12;
             const float2 acc = o[m0];
             if (FUSE == 2) {
                 a.exbar[e] = make_float2(acc.x + th * (acc.x - xo[m0].x), acc.y + th * (acc.y - xo[m0].y));
@@ -700,11 +722,12 @@ __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
 
 static size_t dwt3_lds_bytes() {
     constexpr int IN = 2 * kDwt3B + 6;
-    return sizeof(float2) * (size_t)(IN * IN * IN);
+    return sizeof(float2) * (size_t)(IN * IN * dwt3_row<IN>());
 }
 
 static void dwt3_prox(float2* z, float2* scratch, const int64_t* N, int levels, const DwtFuse& fz, hipStream_t s) {
-    if (N[0] * N[1] * N[2] >= ((int64_t)1 << 31)) fail(KP_ERR_UNSUPPORTED, "wavelet: image too large");
+    if (N[0] * N[1] * N[2] >= ((int64_t)1 << 31) || N[1] * N[2] >= ((int64_t)1 << 24))
+        fail(KP_ERR_UNSUPPORTED, "wavelet: image too large (N < 2^31 and N1 N2 < 2^24 elements)");
     auto level_buf = [&](int l) { return (l % 2 == 0) ? scratch : z; };
     auto args = [&](int l) {
         Dwt3Args a{};
@@ -1073,6 +1096,36 @@ void pdhg_solve_impl(Plan& P, const float2* y, const float* p, int p_kind, const
     }
     copy2(x, x_out, P.Ntot, s);
     if (u_out) permute_to_caller(u, u_out, P.perm.as<int32_t>(), P.M, C, s);
+}
+
+
+// One l1-db4 prox step x = W^H soft(W z) on the plan's image workspaces (z =
+// img[2], x = img[0], xbar = img[1], scratch img[3]) with the deepest level
+// count up to 4 that every N_a allows, as the PDHG loop runs it: a timing aid
+// (the threshold and theta are set to fixed values first).
+void wavelet_prox_stage(Plan& P, hipStream_t s) {
+    int levels = 0;
+    while (levels < 4) {
+        bool ok = true;
+        for (int a = 0; a < P.d; ++a) ok = ok && P.N[a] % (2 << levels) == 0;
+        if (!ok) break;
+        ++levels;
+    }
+    if (levels == 0) fail(KP_ERR_UNSUPPORTED, "wavelet: no level fits the image shape");
+    upload_wavelet_constants();
+    float* tau = P.sched.as<float>() + 8192;
+    float* th = tau + 8192;
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, tau, 1e-3f);
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, th, 1.f);
+    KP_LAUNCH_CHECK();
+    float2* z = P.img[2].as<float2>();
+    DwtFuse fz{tau, 5e-3f, P.img[0].as<float2>(), P.img[1].as<float2>(), th};
+    if (P.d == 3) {
+        dwt3_prox(z, P.img[3].as<float2>(), P.N, levels, fz, s);
+    } else {
+        dwt(z, P.N, P.d, levels, false, s, &fz);
+        dwt(z, P.N, P.d, levels, true, s, &fz);
+    }
 }
 
 

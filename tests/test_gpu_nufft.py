@@ -247,6 +247,24 @@ def test_edge_cases():
     plan.close()
 
 
+def test_profiling_stages():
+    """Every profiling stage runs on a 3D plan (the prox stage with 3 levels:
+    24 = 3 x 8); an unknown stage is refused."""
+    kp = _kp()
+    from paper_1902_09657_amd import _lib
+    L = _lib.load()
+    s = torch.cuda.current_stream()
+    sp = __import__("ctypes").c_void_p(s.cuda_stream)
+    k, maps, _, _ = case((16, 24, 32), 4, 3000, 5, 1.25, 4)
+    plan = _plan(kp, k, (16, 24, 32), maps, 1.25, 4)
+    for st in range(_lib.KP_STAGE_PROX + 1):
+        print("stage", st, flush=True)
+        _lib.check(L.nufft_stage(plan.handle, st, 2, sp))
+    torch.cuda.synchronize()
+    assert L.nufft_stage(plan.handle, _lib.KP_STAGE_PROX + 1, 1, sp) == -1
+    plan.close()
+
+
 def test_wrong_sized_buffers_refused():
     """Buffers whose size differs from the plan's are refused on the host,
     before any launch (the C-ABI only sees bare pointers)."""
