@@ -498,8 +498,18 @@ struct Dwt3Args {
     const float* theta;
 };
 
-constexpr int kDwt3B = 4;
-static_assert((2 * kDwt3B + 6) * (2 * kDwt3B + 6) <= 256, "one thread per line of a brick face");
+// Bricks: B_a coefficients per band along axis a (4 x 4 x 4; the level-0
+// transform of a wide enough image uses 4 x 4 x 8, whose rows along the
+// contiguous axis store 64 / 128 contiguous bytes per band and whose halo is
+// 4.2 instead of 5.4 times the brick).
+template <int B0, int B1, int B2>
+struct Dwt3Brick {
+    static constexpr int IN0 = 2 * B0 + 6, IN1 = 2 * B1 + 6, IN2 = 2 * B2 + 6;  // loaded extents
+    static constexpr int OB0 = 2 * B0, OB1 = 2 * B1, OB2 = 2 * B2;              // brick outputs per axis
+    static constexpr int P2 = IN2 + 1;  // LDS row length along axis 2 (odd, see dwt3_load)
+    static_assert(IN0 * IN1 <= 256 && IN0 * OB2 <= 256 && OB1 * OB2 <= 256, "one thread per line of each pass");
+    static constexpr size_t lds_bytes() { return sizeof(float2) * (size_t)IN0 * IN1 * P2; }
+};
 
 // Brick of this block.  Workgroups go to the 8 XCDs round-robin, so block r
 // runs on XCD r % 8; the bricks are dealt so that each XCD gets one
@@ -517,30 +527,39 @@ __device__ __forceinline__ void dwt3_brick(const Dwt3Args& a, int* q) {
     q[0] = r / a.nb[1];
 }
 
-// Brick load: the (2B + 6)^3 input values into LDS.  Thread t < IN^2 owns
-// the column (u1, u2) = (t / IN, t % IN) of the brick and loads its IN values
-// along axis 0: its axis-1/2 offset is computed once, the axis-0 offsets are
-// the same for the whole block (scalar), and every load of the thread is
-// issued before its first LDS write.  pos(axis, u) gives the element index
-// along an axis of brick row u; the products are 24-bit (N1 N2 < 2^24 is
-// checked on the host).  LDS rows along axis 2 are padded to IN + 1
-// elements: the axis-2 pass reads one row per lane, and rows of an odd
-// number of 8-byte elements put 16 consecutive lanes on 16 different bank
-// pairs (with IN = 14, lanes 8 apart shared banks).
-template <int IN>
-__host__ __device__ constexpr int dwt3_row() { return IN + 1; }
-template <int IN, typename Pos>
+// Brick load: the IN0 x IN1 x IN2 input values into LDS.  A thread owns a
+// column (u1, u2) of the brick (two for bricks with more than 256 columns)
+// and loads its IN0 values along axis 0: its axis-1/2 offset is computed
+// once, the axis-0 offsets are the same for the whole block (scalar), and
+// every load of the thread is issued before its first LDS write.
+// pos(axis, u) gives the element index along an axis of brick row u; the
+// products are 24-bit (N1 N2 < 2^24 is checked on the host).  LDS rows along
+// axis 2 are padded to an odd length: the axis-2 pass reads one row per
+// lane, and rows of an odd number of 8-byte elements put 16 consecutive
+// lanes on 16 different bank pairs (with 14, lanes 8 apart shared banks).
+template <class K, typename Pos>
 __device__ __forceinline__ void dwt3_load(const Dwt3Args& a, float2* buf, Pos pos) {
-    constexpr int P2 = dwt3_row<IN>();
+    constexpr int NCOL = K::IN1 * K::IN2, NR = (NCOL + 255) / 256;
     const int tid = threadIdx.x;
-    if (tid < IN * IN) {
-        const int u1 = tid / IN, u2 = tid - u1 * IN;
-        const float2* src = a.in + __umul24(pos(1, u1), a.S1) + pos(2, u2);
-        float2 v[IN];
+    float2 v[NR][K::IN0];
 #pragma unroll
-        for (int u0 = 0; u0 < IN; ++u0) v[u0] = src[__umul24(pos(0, u0), a.S0)];
+    for (int k = 0; k < NR; ++k) {
+        const int c = tid + 256 * k;
+        if (c < NCOL) {
+            const int u1 = c / K::IN2, u2 = c - u1 * K::IN2;
+            const float2* src = a.in + __umul24(pos(1, u1), a.S1) + pos(2, u2);
 #pragma unroll
-        for (int u0 = 0; u0 < IN; ++u0) buf[(u0 * IN + u1) * P2 + u2] = v[u0];
+            for (int u0 = 0; u0 < K::IN0; ++u0) v[k][u0] = src[__umul24(pos(0, u0), a.S0)];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int c = tid + 256 * k;
+        if (c < NCOL) {
+            const int u1 = c / K::IN2, u2 = c - u1 * K::IN2;
+#pragma unroll
+            for (int u0 = 0; u0 < K::IN0; ++u0) buf[(u0 * K::IN1 + u1) * K::P2 + u2] = v[k][u0];
+        }
     }
 }
 
@@ -582,78 +601,83 @@ __device__ __forceinline__ void dwt3_inv_line(const float2* v, float2* o) {
 
 // Each axis is filtered line by line in place: a thread reads its whole line
 // into registers and writes the 2B outputs over the line's first 2B entries.
-template <int B>
+template <int B0, int B1, int B2>
 __global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
-    constexpr int IN = 2 * B + 6, OB = 2 * B;
-    extern __shared__ float2 buf[];  // [IN][IN][IN + 1]
+    using K = Dwt3Brick<B0, B1, B2>;
+    constexpr int IN0 = K::IN0, IN1 = K::IN1, IN2 = K::IN2, OB0 = K::OB0, OB1 = K::OB1, OB2 = K::OB2, P2 = K::P2;
+    extern __shared__ float2 buf[];  // [IN0][IN1][P2]
     int q[3];
     dwt3_brick(a, q);
     const int tid = threadIdx.x;
     const float tsoft = *a.tau * a.lam;
     const int h0 = a.n[0] / 2, h1 = a.n[1] / 2, h2 = a.n[2] / 2;
-    // input rows 2 k0 .. 2 k0 + 2B + 5 of every axis, periodic: one wrap
-    // needs one subtraction when the extent is at least IN, a loop otherwise
-    // (deep levels of small images)
-    dwt3_load<IN>(a, buf, [&](int ax, int u) {
+    // input rows 2 k B .. 2 k B + 2B + 5 of every axis, periodic: one wrap
+    // needs one subtraction when the extent is at least the loaded extent, a
+    // loop otherwise (deep levels of small images)
+    dwt3_load<K>(a, buf, [&](int ax, int u) {
+        constexpr int Bs[3] = {B0, B1, B2}, INs[3] = {IN0, IN1, IN2};
         const int n = a.n[ax];
-        int sidx = 2 * q[ax] * B + u;
+        int sidx = 2 * q[ax] * Bs[ax] + u;
         sidx -= sidx >= n ? n : 0;
-        if (n < IN)
+        if (n < INs[ax])
             while (sidx >= n) sidx -= n;
         return sidx;
     });
     __syncthreads();
-    constexpr int P2 = dwt3_row<IN>();
-    float2 v[IN], o[OB];
-    if (tid < IN * IN) {  // axis 2: line (i0, i1)
+    if (tid < IN0 * IN1) {  // axis 2: line (i0, i1)
+        float2 v[IN2], o[OB2];
         float2* line = buf + tid * P2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j];
-        dwt3_fwd_line<B, IN>(v, o);
+        for (int j = 0; j < IN2; ++j) v[j] = line[j];
+        dwt3_fwd_line<B2, IN2>(v, o);
 #pragma unroll
-        for (int r = 0; r < OB; ++r) line[r] = o[r];
+        for (int r = 0; r < OB2; ++r) line[r] = o[r];
     }
     __syncthreads();
-    if (tid < IN * OB) {  // axis 1: line (i0, r2)
-        float2* line = buf + (tid / OB) * IN * P2 + tid % OB;
+    if (tid < IN0 * OB2) {  // axis 1: line (i0, r2)
+        float2 v[IN1], o[OB1];
+        float2* line = buf + (tid / OB2) * IN1 * P2 + tid % OB2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * P2];
-        dwt3_fwd_line<B, IN>(v, o);
+        for (int j = 0; j < IN1; ++j) v[j] = line[j * P2];
+        dwt3_fwd_line<B1, IN1>(v, o);
 #pragma unroll
-        for (int r = 0; r < OB; ++r) line[r * P2] = o[r];
+        for (int r = 0; r < OB1; ++r) line[r * P2] = o[r];
     }
     __syncthreads();
-    if (tid < OB * OB) {  // axis 0: line (r1, r2), soft threshold, store
-        const int r1 = tid / OB, r2 = tid % OB;
+    if (tid < OB1 * OB2) {  // axis 0: line (r1, r2), soft threshold, store
+        float2 v[IN0], o[OB0];
+        const int r1 = tid / OB2, r2 = tid % OB2;
         const float2* line = buf + r1 * P2 + r2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * P2];
-        dwt3_fwd_line<B, IN>(v, o);
-        const int c1 = q[1] * B + (r1 < B ? r1 : r1 - B);
-        const int c2 = q[2] * B + (r2 < B ? r2 : r2 - B);
+        for (int j = 0; j < IN0; ++j) v[j] = line[j * IN1 * P2];
+        dwt3_fwd_line<B0, IN0>(v, o);
+        const int c1 = q[1] * B1 + (r1 < B1 ? r1 : r1 - B1);
+        const int c2 = q[2] * B2 + (r2 < B2 ? r2 : r2 - B2);
         if (c1 >= h1 || c2 >= h2) return;  // past the block (last brick of an axis)
-        const int p12 = __umul24(r1 < B ? c1 : h1 + c1, a.S1) + (r2 < B ? c2 : h2 + c2);
+        const int p12 = __umul24(r1 < B1 ? c1 : h1 + c1, a.S1) + (r2 < B2 ? c2 : h2 + c2);
 #pragma unroll
-        for (int r0 = 0; r0 < OB; ++r0) {
-            const int c0 = q[0] * B + (r0 < B ? r0 : r0 - B);
+        for (int r0 = 0; r0 < OB0; ++r0) {
+            const int c0 = q[0] * B0 + (r0 < B0 ? r0 : r0 - B0);
             if (c0 >= h0) continue;
             float2 acc = o[r0];
-            if (a.soft == 2 || r0 >= B || r1 >= B || r2 >= B) {
+            if (a.soft == 2 || r0 >= B0 || r1 >= B1 || r2 >= B2) {
                 const float m2 = acc.x * acc.x + acc.y * acc.y;
                 const float g = m2 > tsoft * tsoft ? 1.f - tsoft * rsqrtf(m2) : 0.f;
                 acc = make_float2(acc.x * g, acc.y * g);
             }
-            a.out[__umul24(r0 < B ? c0 : h0 + c0, a.S0) + p12] = acc;
+            a.out[__umul24(r0 < B0 ? c0 : h0 + c0, a.S0) + p12] = acc;
         }
     }
 }
 
 // x[m] = sum_q h[t] a[(m - t) / 2] + g[t] d[(m - t) / 2], t = (m & 1) + 2q,
-// indices mod n / 2; the brick holds a, d at k0 - 3 .. k0 + B - 1 (B + 3 each)
-template <int B, int FUSE>
+// indices mod n / 2; along axis a the brick holds a, d at k0 - 3 .. k0 +
+// B_a - 1 (B_a + 3 each)
+template <int B0, int B1, int B2, int FUSE>
 __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
-    constexpr int NB = B + 3, IN = 2 * NB, OB = 2 * B;
-    extern __shared__ float2 buf[];  // [IN][IN][IN + 1] (per axis: low band u < NB, high band NB + u)
+    using K = Dwt3Brick<B0, B1, B2>;
+    constexpr int IN0 = K::IN0, IN1 = K::IN1, IN2 = K::IN2, OB0 = K::OB0, OB1 = K::OB1, OB2 = K::OB2, P2 = K::P2;
+    extern __shared__ float2 buf[];  // [IN0][IN1][P2] (per axis: low band u < NB, high band NB + u)
     int q[3];
     dwt3_brick(a, q);
     const int tid = threadIdx.x;
@@ -661,23 +685,24 @@ __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
     const int hh[3] = {a.n[0] / 2, a.n[1] / 2, a.n[2] / 2};
     // x_old of the line a last-pass thread will write, loaded first so that
     // its latency hides behind the brick load and the first two passes
-    float2 xo[OB];
-    const int m1 = tid / OB, m2 = tid % OB;
-    const int g1 = 2 * q[1] * B + m1, g2 = 2 * q[2] * B + m2;
-    const bool tail = tid < OB * OB && g1 < a.n[1] && g2 < a.n[2];
+    float2 xo[OB0];
+    const int m1 = tid / OB2, m2 = tid % OB2;
+    const int g1 = 2 * q[1] * B1 + m1, g2 = 2 * q[2] * B2 + m2;
+    const bool tail = tid < OB1 * OB2 && g1 < a.n[1] && g2 < a.n[2];
     const int e12 = __umul24(g1, a.S1) + g2;
     if (FUSE == 2 && tail) {
 #pragma unroll
-        for (int m0 = 0; m0 < OB; ++m0) {
-            const int g0 = min(2 * q[0] * B + m0, a.n[0] - 1);
+        for (int m0 = 0; m0 < OB0; ++m0) {
+            const int g0 = min(2 * q[0] * B0 + m0, a.n[0] - 1);
             xo[m0] = a.ex[__umul24(g0, a.S0) + e12];
         }
     }
     // coefficient k0 - 3 + u of each band, periodic in [0, h): one
-    // correction each way when h >= NB, a loop otherwise
-    dwt3_load<IN>(a, buf, [&](int ax, int u) {
-        const int h = hh[ax];
-        int kk = q[ax] * B - 3 + (u >= NB ? u - NB : u);
+    // correction each way when h >= B + 3, a loop otherwise
+    dwt3_load<K>(a, buf, [&](int ax, int u) {
+        constexpr int Bs[3] = {B0, B1, B2};
+        const int h = hh[ax], NB = Bs[ax] + 3;
+        int kk = q[ax] * Bs[ax] - 3 + (u >= NB ? u - NB : u);
         kk += kk < 0 ? h : 0;
         kk -= kk >= h ? h : 0;
         if (h < NB) {
@@ -687,34 +712,35 @@ __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
         return (u >= NB ? h : 0) + kk;
     });
     __syncthreads();
-    constexpr int P2 = dwt3_row<IN>();
-    float2 v[IN], o[OB];
-    if (tid < IN * IN) {
+    if (tid < IN0 * IN1) {  // axis 2
+        float2 v[IN2], o[OB2];
         float2* line = buf + tid * P2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j];
-        dwt3_inv_line<B>(v, o);
+        for (int j = 0; j < IN2; ++j) v[j] = line[j];
+        dwt3_inv_line<B2>(v, o);
 #pragma unroll
-        for (int m = 0; m < OB; ++m) line[m] = o[m];
+        for (int m = 0; m < OB2; ++m) line[m] = o[m];
     }
     __syncthreads();
-    if (tid < IN * OB) {
-        float2* line = buf + (tid / OB) * IN * P2 + tid % OB;
+    if (tid < IN0 * OB2) {  // axis 1
+        float2 v[IN1], o[OB1];
+        float2* line = buf + (tid / OB2) * IN1 * P2 + tid % OB2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * P2];
-        dwt3_inv_line<B>(v, o);
+        for (int j = 0; j < IN1; ++j) v[j] = line[j * P2];
+        dwt3_inv_line<B1>(v, o);
 #pragma unroll
-        for (int m = 0; m < OB; ++m) line[m * P2] = o[m];
+        for (int m = 0; m < OB1; ++m) line[m * P2] = o[m];
     }
     __syncthreads();
-    if (tail) {
+    if (tail) {  // axis 0, store (and the x / xbar update on level 0)
+        float2 v[IN0], o[OB0];
         const float2* line = buf + m1 * P2 + m2;
 #pragma unroll
-        for (int j = 0; j < IN; ++j) v[j] = line[j * IN * P2];
-        dwt3_inv_line<B>(v, o);
+        for (int j = 0; j < IN0; ++j) v[j] = line[j * IN1 * P2];
+        dwt3_inv_line<B0>(v, o);
 #pragma unroll
-        for (int m0 = 0; m0 < OB; ++m0) {
-            const int g0 = 2 * q[0] * B + m0;
+        for (int m0 = 0; m0 < OB0; ++m0) {
+            const int g0 = 2 * q[0] * B0 + m0;
             if (g0 >= a.n[0]) continue;
             const int e = __umul24(g0, a.S0) + e12;
             const float2 acc = o[m0];
@@ -728,9 +754,21 @@ __global__ void __launch_bounds__(256) k_dwt3_synthesis(Dwt3Args a) {
     }
 }
 
-static size_t dwt3_lds_bytes() {
-    constexpr int IN = 2 * kDwt3B + 6;
-    return sizeof(float2) * (size_t)(IN * IN * dwt3_row<IN>());
+// launches of one level with the bricks of K
+template <int B0, int B1, int B2>
+static void dwt3_level(Dwt3Args a, bool analysis, int fuse, hipStream_t s) {
+    using K = Dwt3Brick<B0, B1, B2>;
+    const int Bs[3] = {B0, B1, B2};
+    for (int b = 0; b < 3; ++b) a.nb[b] = (a.n[b] / 2 + Bs[b] - 1) / Bs[b];
+    const dim3 grid((unsigned)(a.nb[0] * a.nb[1] * a.nb[2]));
+    const size_t lds = K::lds_bytes();
+    if (analysis)
+        hipLaunchKernelGGL((k_dwt3_analysis<B0, B1, B2>), grid, dim3(256), lds, s, a);
+    else if (fuse == 2)
+        hipLaunchKernelGGL((k_dwt3_synthesis<B0, B1, B2, 2>), grid, dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_dwt3_synthesis<B0, B1, B2, 0>), grid, dim3(256), lds, s, a);
+    KP_LAUNCH_CHECK();
 }
 
 static void dwt3_prox(float2* z, float2* scratch, const int64_t* N, int levels, const DwtFuse& fz, hipStream_t s) {
@@ -741,13 +779,16 @@ static void dwt3_prox(float2* z, float2* scratch, const int64_t* N, int levels, 
         Dwt3Args a{};
         a.S0 = (int)(N[1] * N[2]);
         a.S1 = (int)N[2];
-        for (int b = 0; b < 3; ++b) {
-            a.n[b] = (int)(N[b] >> l);
-            a.nb[b] = (a.n[b] / 2 + kDwt3B - 1) / kDwt3B;
-        }
+        for (int b = 0; b < 3; ++b) a.n[b] = (int)(N[b] >> l);
         return a;
     };
-    const size_t lds = dwt3_lds_bytes();
+    // level 0 of an image at least 32 wide along axis 2 on 4 x 4 x 8 bricks
+    auto launch = [&](int l, const Dwt3Args& a, bool analysis, int fuse) {
+        if (l == 0 && a.n[2] >= 32)
+            dwt3_level<4, 4, 8>(a, analysis, fuse, s);
+        else
+            dwt3_level<4, 4, 4>(a, analysis, fuse, s);
+    };
     for (int l = 0; l < levels; ++l) {
         Dwt3Args a = args(l);
         a.in = l == 0 ? z : level_buf(l - 1);
@@ -755,23 +796,20 @@ static void dwt3_prox(float2* z, float2* scratch, const int64_t* N, int levels, 
         a.soft = l == levels - 1 ? 2 : 1;
         a.tau = fz.tau;
         a.lam = fz.lam;
-        hipLaunchKernelGGL(k_dwt3_analysis<kDwt3B>, dim3((unsigned)(a.nb[0] * a.nb[1] * a.nb[2])), dim3(256), lds, s, a);
-        KP_LAUNCH_CHECK();
+        launch(l, a, true, 0);
     }
     for (int l = levels - 1; l >= 0; --l) {
         Dwt3Args a = args(l);
         a.in = level_buf(l);
-        const dim3 grid((unsigned)(a.nb[0] * a.nb[1] * a.nb[2]));
         if (l == 0) {
             a.ex = fz.ex;
             a.exbar = fz.exbar;
             a.theta = fz.theta;
-            hipLaunchKernelGGL((k_dwt3_synthesis<kDwt3B, 2>), grid, dim3(256), lds, s, a);
+            launch(l, a, false, 2);
         } else {
             a.out = level_buf(l - 1);
-            hipLaunchKernelGGL((k_dwt3_synthesis<kDwt3B, 0>), grid, dim3(256), lds, s, a);
+            launch(l, a, false, 0);
         }
-        KP_LAUNCH_CHECK();
     }
 }
 
