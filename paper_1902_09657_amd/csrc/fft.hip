@@ -873,15 +873,19 @@ static fft_kernel_t fixed_for(int L) {
 
 // register-resident passes: plain 32-column passes of lengths 8 x N2 with an
 // N2-point DFT small enough for registers
-// register-resident passes: plain 32-column passes of lengths 8 x N2 with an
-// N2-point DFT small enough for registers.  The fused map passes stay on the
-// LDS-staged kernel: 25 values per lane cap a register pass at about 11
-// waves per CU, and those passes ran slower in that form.
-static fft_kernel_t reg_for(const FftPass& p) {
+// register-resident passes: plain 32-column passes of lengths N1 x N2 with
+// an N2-point DFT small enough for registers, on N1 x 32 threads.  200 = 10 x
+// 20 balances both steps (2 step-1 tasks per thread, one step-2 task; 8 x 25
+// left a 4th step-1 task to an eighth of the threads: FFT stages 0.445 ->
+// 0.433 ms forward); the other lengths use N1 = 8.  The fused map passes stay
+// on the LDS-staged kernel: 25 values per lane cap a register pass at about
+// 11 waves per CU, and those passes ran slower in that form.
+static fft_kernel_t reg_for(const FftPass& p, int* n1) {
     if (p.pre != PRE_NONE || p.post != POST_NONE || p.Ob * p.Ib != 32) return nullptr;
+    *n1 = 8;
     switch (p.L) {
         case 160: return k_fft_reg<160, 8, 32>;
-        case 200: return k_fft_reg<200, 8, 32>;
+        case 200: *n1 = 10; return k_fft_reg<200, 10, 32>;
         case 240: return k_fft_reg<240, 8, 32>;
         case 256: return k_fft_reg<256, 8, 32>;
         default: return nullptr;
@@ -900,7 +904,8 @@ static bool reg_span_ok(const FftPass& p) {
 // try the specialised kernels; false if this pass fits neither
 static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     const int nc = p.Ob * p.Ib;
-    fft_kernel_t fr = reg_for(p);
+    int n1 = 8;
+    fft_kernel_t fr = reg_for(p, &n1);
     if (fr && reg_span_ok(p)) {
         const size_t lds = sizeof(float2) * (size_t)p.L * 33;
         if (lds <= (size_t)lim) {
@@ -911,7 +916,7 @@ static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
             const int64_t nblk = fft_pass_blocks(p);
             if (nblk <= 0) return true;
             if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "FFT pass grid too large");
-            hipLaunchKernelGGL(fr, dim3((unsigned)nblk), dim3(8 * 32), lds, s, p);
+            hipLaunchKernelGGL(fr, dim3((unsigned)nblk), dim3(n1 * 32), lds, s, p);
             KP_LAUNCH_CHECK();
             return true;
         }
