@@ -229,6 +229,7 @@ struct Plan {
 
     DevBuf coords;                // caller's coordinates [M][d]
     DevBuf g_sorted, g_orig, perm, bin_off, touch_off, touch, work, heavy_list;
+    DevBuf iperm;                 // inverse of perm: sorted position of caller sample j
     DevBuf stouch, scode;         // touch entries in spreading order, their buckets
     DevBuf xrange;                // 3D: axis-0 cell range of the non-empty spreading tiles per (ty, tz)
     DevBuf yrange;                // 3D: axis-1 cell range of the tile columns with a non-empty tile, per tz
@@ -314,8 +315,11 @@ void launch_reduce_batch(const SpreadArgs* d_args, const int2* d_hv, const int4*
 void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, hipStream_t s);
 
 // Elementwise helpers (solver.hip)
+// (with iperm, the inverse permutation, for C = 2, 4, 8 or 12: one thread
+// per caller sample, coalesced reads of the coil rows, one contiguous run of
+// 16-byte stores per sample at its sorted position)
 void permute_to_internal(const float2* y_caller, float2* kint, const int32_t* perm, int64_t M,
-                         int C, hipStream_t s);
+                         int C, hipStream_t s, const int32_t* iperm = nullptr);
 void permute_to_caller(const float2* kint, float2* y_caller, const int32_t* perm, int64_t M,
                        int C, hipStream_t s);
 void permute_p_to_internal(const float* p_caller, float* pint, const int32_t* perm, int64_t M,

@@ -221,6 +221,11 @@ __global__ void k_coords(const float* k, int64_t M, Geom gm, float* g, uint32_t*
     key[s] = kk;
 }
 
+__global__ void k_invert_perm(const int32_t* perm, int32_t* iperm, int64_t n) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) iperm[perm[s]] = (int32_t)s;
+}
+
 __global__ void k_iota(int32_t* v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) v[i] = (int32_t)i;
@@ -641,6 +646,9 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     hipLaunchKernelGGL(k_gather_coords, dim3(nblk(M)), dim3(256), 0, s, P->g_orig.as<float>(),
                        P->perm.as<int32_t>(), M, d, P->g_sorted.as<float>());
     KP_LAUNCH_CHECK();
+    P->iperm.alloc(sizeof(int32_t) * M);
+    hipLaunchKernelGGL(k_invert_perm, dim3(nblk(M)), dim3(256), 0, s, P->perm.as<int32_t>(), P->iperm.as<int32_t>(), M);
+    KP_LAUNCH_CHECK();
 
     // ---- tile touch lists
     DevBuf tcnt;
@@ -891,7 +899,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_HIP(hipStreamSynchronize(s));
 
     int64_t total = 0;
-    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->bin_off, &P->xrange, &P->yrange, &P->touch_off, &P->touch, &P->work,
+    for (DevBuf* b : {&P->partial, &P->coords, &P->g_sorted, &P->g_orig, &P->perm, &P->iperm, &P->bin_off, &P->xrange, &P->yrange, &P->touch_off, &P->touch, &P->work,
                       &P->heavy_list, &P->maps, &P->fo_fwd, &P->fr_fwd, &P->bufA, &P->bufB, &P->kint, &P->kint2, &P->kint3,
                       &P->pint, &P->red, &P->sched, &P->tvv, &P->kint4})
         total += (int64_t)b->bytes;
@@ -1226,7 +1234,8 @@ int nufft_adjoint(kp_plan_t plan, const void* y, void* x, void* stream) {
         Plan& P = *plan->impl;
         hipStream_t s = (hipStream_t)stream;
         P.stream = s;
-        permute_to_internal((const float2*)y, P.kint.as<float2>(), P.perm.as<int32_t>(), P.M, (int)P.C, s);
+        permute_to_internal((const float2*)y, P.kint.as<float2>(), P.perm.as<int32_t>(), P.M, (int)P.C, s,
+                            P.iperm.as<int32_t>());
         float2* grid = spread_to_grid(P, P.kint.as<float2>(), (int)P.C, s);
         AdjOpts ao;
         grid_to_image(P, grid, (float2*)x, ao, s);

@@ -71,8 +71,38 @@ __global__ void k_perm_in_c(const float2* __restrict__ y, float2* __restrict__ k
     for (int q = 0; q < C / 2; ++q) dst[q] = make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
 }
 
-void permute_to_internal(const float2* y, float2* k, const int32_t* perm, int64_t M, int C, hipStream_t s) {
+// One thread per caller sample j (inverse permutation): every load
+// instruction of a wave reads 64 consecutive caller samples of one coil row,
+// and each thread stores its sample's C values as one contiguous run of
+// 16-byte stores at its sorted position iperm[j].
+template <int C>
+__global__ void k_perm_in_inv_c(const float2* __restrict__ y, float2* __restrict__ k, const int32_t* __restrict__ iperm,
+                                int64_t M) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    float2 v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = y[(int64_t)c * M + j];
+    float4* dst = reinterpret_cast<float4*>(k + (int64_t)iperm[j] * C);
+#pragma unroll
+    for (int q = 0; q < C / 2; ++q) dst[q] = make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
+}
+
+void permute_to_internal(const float2* y, float2* k, const int32_t* perm, int64_t M, int C, hipStream_t s,
+                         const int32_t* iperm) {
     if (M <= 0) return;
+    if (iperm && (C == 8 || C == 12 || C == 4 || C == 2)) {
+        if (C == 8)
+            hipLaunchKernelGGL(k_perm_in_inv_c<8>, dim3(nblk(M)), dim3(256), 0, s, y, k, iperm, M);
+        else if (C == 12)
+            hipLaunchKernelGGL(k_perm_in_inv_c<12>, dim3(nblk(M)), dim3(256), 0, s, y, k, iperm, M);
+        else if (C == 4)
+            hipLaunchKernelGGL(k_perm_in_inv_c<4>, dim3(nblk(M)), dim3(256), 0, s, y, k, iperm, M);
+        else
+            hipLaunchKernelGGL(k_perm_in_inv_c<2>, dim3(nblk(M)), dim3(256), 0, s, y, k, iperm, M);
+        KP_LAUNCH_CHECK();
+        return;
+    }
     if (C == 8)
         hipLaunchKernelGGL(k_perm_in_c<8>, dim3(nblk(M)), dim3(256), 0, s, y, k, perm, M);
     else if (C == 12)
@@ -1035,10 +1065,10 @@ void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_p
     // y, p, u, x into internal layouts
     float2* yint = P.kint2.as<float2>();
     float2* u = P.kint.as<float2>();
-    permute_to_internal(y, yint, P.perm.as<int32_t>(), P.M, C, s);
+    permute_to_internal(y, yint, P.perm.as<int32_t>(), P.M, C, s, P.iperm.as<int32_t>());
     const float* pint = load_p(P, p, p_kind, s);
     if (op.u0)
-        permute_to_internal((const float2*)op.u0, u, P.perm.as<int32_t>(), P.M, C, s);
+        permute_to_internal((const float2*)op.u0, u, P.perm.as<int32_t>(), P.M, C, s, P.iperm.as<int32_t>());
     else
         fill2(u, P.M * C, 0.f, 0.f, s);
     float2* x = P.img[0].as<float2>();
@@ -1262,7 +1292,7 @@ void l2_dual_cg_impl(Plan& P, const float2* y, const float* p, int p_kind, float
     float2* img = P.img[0].as<float2>();
     double* sl = P.red.as<double>() + 2048;  // rz (two slots), dq, |r|^2, |r0|^2
     double* part = P.red.as<double>() + 16;
-    permute_to_internal(y, r, P.perm.as<int32_t>(), P.M, C, s);
+    permute_to_internal(y, r, P.perm.as<int32_t>(), P.M, C, s, P.iperm.as<int32_t>());
     const float* pint = load_p(P, p, p_kind, s);
     hipLaunchKernelGGL(k_cg_init, dim3(nblk(n)), dim3(256), 0, s, r, u, d, pint, p_mc, C, n, lam);
     KP_LAUNCH_CHECK();

@@ -221,7 +221,8 @@ static void load_inputs(Plan& P, const void* y, const float* p, int p_kind, USta
     if (p_kind != KP_PRECOND_NONE && p_kind != KP_PRECOND_SC && p_kind != KP_PRECOND_MC)
         fail(KP_ERR_INVALID_ARG, "p_kind must be NONE, SC or MC");
     if (p_kind != KP_PRECOND_NONE && !p) fail(KP_ERR_INVALID_ARG, "p is NULL");
-    permute_to_internal((const float2*)y, P.kint2.as<float2>(), P.perm.as<int32_t>(), P.M, (int)P.C, s);
+    permute_to_internal((const float2*)y, P.kint2.as<float2>(), P.perm.as<int32_t>(), P.M, (int)P.C, s,
+                        P.iperm.as<int32_t>());
     U.y = P.kint2.as<float2>();
     U.p = load_p(P, p, p_kind, s);
     U.p_mc = p_kind == KP_PRECOND_MC ? 1 : 0;
