@@ -728,9 +728,12 @@ int spread_threads(int d, const int* B, int C) {
 }
 
 // LDS carve-up for a chunk of E entries (all 4-byte words):
-//   code[E] | wl[(d-1) W][E+1] | wz[ZM][E] | u[C][E+1] (float2) | bstart[NBK+1]
-// (rows of wl and u padded by one element: lanes reading one entry from
-// different rows, or different coil groups, fall into different banks)
+//   code[E] | wl[(d-1) W][E+1] | wz[ZM][E] | u[C/CG][CG][E] (float2, each coil
+//   group padded by one element; C E + C/CG <= C (E+1)) | bstart[NBK+1]
+// (rows of wl padded by one element and coil groups by one float2: lanes
+// reading one entry from different rows, or for different coil groups, fall
+// into different banks; within a group the CG coils of an entry are E float2
+// apart, so one base register and two ds_read2st64_b64 reach all four)
 // (entry index fastest, so lanes reading different entries hit different banks)
 // buckets of a tile: first-tap positions -(W-1) .. B_a - 1 on the leading axes
 int spread_nbk(int d, int W, const int* B) {
@@ -771,7 +774,8 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
     int* code = smem;
     float* wl = (float*)(code + E);
     float* wz = wl + EP * NLW;
-    float2* uu = (float2*)(wz + E * ZM);
+    float2* uu = (float2*)(wz + E * ZM);  // [C / CG][CG][E], each coil group padded by one element
+    constexpr int UG = CG * E + 1;        // coil-group stride of uu
     int* bstart = (int*)(uu + EP * C);
 
     const int4 wk = a.work[item];
@@ -834,7 +838,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
         if (uv) {
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if (c < C) uu[c * EP + e] = uv[c];
+                if (c < C) uu[(c / CG) * UG + (c % CG) * E + e] = uv[c];
         }
     };
     // pipeline registers (PF): data of the current chunk's entry tid, touch
@@ -873,7 +877,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
 #pragma unroll
                 for (int ax = 0; ax < D; ++ax) gv[ax] = a.g[(int64_t)s * D + ax];
                 const float2* src = a.k + (int64_t)s * C;
-                for (int c = 0; c < C; ++c) uu[c * EP + e] = src[c];
+                for (int c = 0; c < C; ++c) uu[(c / CG) * UG + (c % CG) * E + e] = src[c];
                 stage(e, a.code[start + c0 + e], gv, nullptr);
             }
         }
@@ -907,10 +911,10 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const KbParams&
             auto gather = [&](int idx, const float* wrow) {
                 float wA = wrow[idx];
                 if (D == 3) wA *= *reinterpret_cast<const float*>(wly + (code[idx] >> 16));
-                const float2* up = uu + (cg * CG) * EP + idx;
+                const float2* up = uu + cg * UG + idx;
                 float2 uv[CG];
 #pragma unroll
-                for (int c = 0; c < CG; ++c) uv[c] = up[c * EP];
+                for (int c = 0; c < CG; ++c) uv[c] = up[c * E];
 #pragma unroll
                 for (int z = 0; z < ZM; ++z) {
                     const float wt = wA * wz[z * E + idx];
