@@ -8,6 +8,12 @@
 // N non-zero input rows (centred placement n mod L, the zero rows are never
 // read) and an adjoint pass writes only the N kept output rows (centred crop).
 //
+// Three kernels share this contract: the general pass (any length, two LDS
+// buffers), the specialised LDS-staged pass (compile-time length and column
+// block, stages in place in one buffer) and, for plain 32-column passes of
+// lengths 160, 200, 240 and 256, a register-resident two-factor pass (one
+// LDS transpose per pass; below).
+//
 // The first forward pass along the last image axis fuses the pre-pass of the
 // NUFFT (coil multiply x s_c, deapodisation 1/(sqrt(N) Chat), and the sign
 // (-1)^n that centres the spectrum so grid cell G/2 is k = 0); the last
