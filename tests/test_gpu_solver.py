@@ -129,6 +129,9 @@ SOLVE_CASES = [
     # updates fused into its coil-sum pass
     ((16, 16, 128), 4, 4000, 1.25, 4, "l2", 1e-3, "mc", 8, 2),
     ((16, 16, 128), 8, 4000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 2),
+    # 4 x 4 x 8 level-0 bricks with axes shorter than the loaded brick (8 < 14:
+    # the periodic wrap takes its loop), deepest level two samples long
+    ((8, 8, 64), 2, 2000, 1.25, 4, "l1wav", 5e-3, "sc", 6, 2),
 ]
 
 
