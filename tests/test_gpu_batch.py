@@ -47,9 +47,10 @@ def make_batch(kp, sl, tune, alpha=1.25, W=4):
     return kp.nufft_plan_batch(coords, [s for s, _, _, _ in sl], maps, oversamp=alpha, kb_width=W, tune=tune)
 
 
-def plain_solve(kp, sh, k, maps, y, p, alpha, W, bin_size=None, **kw):
+def plain_solve(kp, sh, k, maps, y, p, alpha, W, bin_size=None, max_chunk=0, spread_bin_size=None, **kw):
     plan = kp.nufft_plan(dev(k, torch.float32), sh, None if maps is None else dev(maps, torch.complex64),
-                         oversamp=alpha, kb_width=W, bin_size=bin_size)
+                         oversamp=alpha, kb_width=W, bin_size=bin_size, max_chunk=max_chunk,
+                         spread_bin_size=spread_bin_size)
     x = kp.pdhg_solve(plan, dev(y, torch.complex64), p, reg="l2", **kw)
     plan.close()
     return x
@@ -91,12 +92,13 @@ def test_batch_tuned_equals_plain_same_tiles():
     for i, (sh, k, maps, y) in enumerate(sl):
         inf = kp.nufft_batch_info(b, i)
         assert inf["fast"]
-        xp = plain_solve(kp, sh, k, maps, y, None, 1.25, 4, bin_size=inf["bin_size"], lam=1e-2, iters=8,
-                         lambda_max=lm[i])
+        # the plain plan takes the tuned tiles and split size, so both sides
+        # sum in the same order
+        xp = plain_solve(kp, sh, k, maps, y, None, 1.25, 4, bin_size=inf["bin_size"], max_chunk=inf["max_chunk"],
+                         spread_bin_size=inf["spread_bin_size"], lam=1e-2, iters=8, lambda_max=lm[i])
         r = rel(xb[i].cpu().numpy(), xp.cpu().numpy())
-        print("slice", i, sh, inf["bin_size"], "rel", r, flush=True)
-        # split sizes may differ from the plain default: summation order only
-        assert r < 1e-5
+        print("slice", i, sh, inf["bin_size"], inf["spread_bin_size"], inf["max_chunk"], "rel", r, flush=True)
+        assert r < 1e-6
     b.close()
 
 
