@@ -186,6 +186,36 @@ def test_dense_centre_3d(C, bins):
     plan.close()
 
 
+@pytest.mark.parametrize("shape,sbins,chunk", [
+    ((32, 32, 32), (8, 8, 4), 0),      # grid 40^3 in the default 3D spreading tiles
+    ((32, 32, 32), (8, 8, 2), 0),      # shallower tiles
+    ((32, 64, 24), (4, 16, 3), 0),     # 64 lines as 4 x 16, 3 cells deep
+    ((32, 32, 32), (8, 8, 4), 128),    # every busy tile split: partial tiles added in slot order
+])
+def test_spread_eight_coils_two_threads_per_line(shape, sbins, chunk):
+    """8 coils and 64 lines per spreading tile: two threads per line, each
+    with every coil, the entries of a line split between them."""
+    kp = _kp()
+    C, M = 8, 12000
+    k, maps, x, y = case(shape, C, M, 21, 1.25, 4)
+    k[300:1500] = 0.0                    # a dense centre
+    print("spread 8 coils", shape, sbins, chunk, flush=True)
+    op = onufft.Nufft(k, shape, maps, 1.25, 4)
+    plan = _plan(kp, k, shape, maps, 1.25, 4, spread_bin_size=sbins, max_chunk=chunk)
+    info = plan.info()
+    assert info["spread_bin_size"] == sbins
+    if chunk:
+        assert info["heavy_tiles"] > 0
+    xg = kp.nufft_adjoint(plan, dev(y, torch.complex64)).cpu().numpy()
+    assert rel(xg, op.adjoint(y)) < 1e-4
+    for i in range(NSPECIAL):
+        yi = np.zeros((C, M), np.complex128)
+        yi[i % C, i] = 1.0
+        e = rel(kp.nufft_adjoint(plan, dev(yi, torch.complex64)).cpu().numpy(), op.adjoint(yi))
+        assert e < 1e-4, (i, k[i], e)
+    plan.close()
+
+
 def test_adjoint_identity_on_gpu():
     kp = _kp()
     shape, C = (20, 24, 16), 3
