@@ -20,6 +20,9 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
  *    stream-ordered and asynchronous unless its comment says otherwise.  A
  *    plan serves one stream at a time and is not re-entrant.
+ *  - A plan (and a batch) belongs to the device that was current when it was
+ *    made; every later call on it must run with that device current, else it
+ *    fails with KP_ERR_INVALID_ARG (the library never switches devices).
  *  - Every call returns KP_OK or a negative status and never throws; the
  *    message of the last failure on the calling thread is kp_last_error().
  *    Asynchronous kernel faults surface as KP_ERR_HIP at the next checked

@@ -461,6 +461,7 @@ int pdhg_solve_batch(kp_batch_t batch, const void* const* y, const float* const*
         if (p_kind != KP_PRECOND_NONE && !p) fail(KP_ERR_INVALID_ARG, "p is NULL");
         hipStream_t s = (hipStream_t)stream;
         const int n = (int)B.plans.size();
+        require_plan_device(*B.plans[0]);
         for (int i = 0; i < n; ++i) {
             kp_pdhg_opts oi = op;
             if (lambda_max) {

@@ -201,6 +201,7 @@ void launch_reduce_partials(const SpreadArgs& a, const int4* heavy, int nheavy, 
 
 // ------------------------------------------------------------ plan
 struct Plan {
+    int dev = 0;          // device current when the plan was made; every call on it must run there
     int d = 0;
     int64_t N[3] = {1, 1, 1};
     int64_t Ntot = 0;
@@ -255,6 +256,10 @@ struct Plan {
     std::vector<int> fft_rad[3];
     int64_t bytes = 0;
 };
+
+// fails (KP_ERR_INVALID_ARG) unless the plan's device is the current one:
+// the library never switches devices, and a plan's buffers live on one
+void require_plan_device(const Plan& P);
 
 Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsamples,
                   const float* coords, const void* maps, float oversamp, int kb_width,

@@ -48,6 +48,7 @@ int nufft_forward_noalloc(kp_plan_t plan, const void* x, void* y, void* stream) 
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
         if (!x || !y) fail(KP_ERR_INVALID_ARG, "x or y is NULL");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         const size_t need = sizeof(float2) * (size_t)P.Gtot * (size_t)P.C;
         if (need > kNoallocGridBytes)
             fail(KP_ERR_UNSUPPORTED, "nufft_forward_noalloc: the oversampled grid needs " + std::to_string(need) +

@@ -553,6 +553,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
 
     int dev = 0;
     KP_HIP(hipGetDevice(&dev));
+    P->dev = dev;
     hipDeviceProp_t prop;
     KP_HIP(hipGetDeviceProperties(&prop, dev));
     P->lds_max = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
@@ -1176,6 +1177,14 @@ std::vector<double> db4_filter_host() {
     return h;
 }
 
+void require_plan_device(const Plan& P) {
+    int cur = 0;
+    KP_HIP(hipGetDevice(&cur));
+    if (cur != P.dev)
+        fail(KP_ERR_INVALID_ARG, "the plan belongs to device " + std::to_string(P.dev) + " but device " +
+                                     std::to_string(cur) + " is current");
+}
+
 }  // namespace kp
 
 // ================================================================== C ABI
@@ -1216,6 +1225,7 @@ int nufft_forward(kp_plan_t plan, const void* x, void* y, void* stream) {
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
         if (!x || !y) fail(KP_ERR_INVALID_ARG, "x or y is NULL");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         hipStream_t s = (hipStream_t)stream;
         P.stream = s;
         FwdOpts fo;
@@ -1232,6 +1242,7 @@ int nufft_adjoint(kp_plan_t plan, const void* y, void* x, void* stream) {
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
         if (!x || !y) fail(KP_ERR_INVALID_ARG, "x or y is NULL");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         hipStream_t s = (hipStream_t)stream;
         P.stream = s;
         permute_to_internal((const float2*)y, P.kint.as<float2>(), P.perm.as<int32_t>(), P.M, (int)P.C, s,
@@ -1274,6 +1285,7 @@ int nufft_plan_sort(kp_plan_t plan, int32_t* perm, int32_t* bin_offsets, int32_t
     return guarded([&] {
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         hipStream_t s = (hipStream_t)stream;
         if (perm) KP_HIP(hipMemcpyAsync(perm, P.perm.p, sizeof(int32_t) * P.M, hipMemcpyDeviceToDevice, s));
         if (bin_offsets)
@@ -1289,6 +1301,7 @@ int nufft_plan_grid_coords(kp_plan_t plan, float* g, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl || !g) fail(KP_ERR_INVALID_ARG, "NULL argument");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         KP_HIP(hipMemcpyAsync(g, P.g_orig.p, sizeof(float) * P.M * P.d, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     });
 }
@@ -1299,6 +1312,7 @@ int nufft_stage(kp_plan_t plan, int stage, int reps, void* stream) {
         if (stage < 0 || stage > KP_STAGE_PROX) fail(KP_ERR_INVALID_ARG, "unknown stage");
         if (reps < 1) fail(KP_ERR_INVALID_ARG, "reps must be >= 1");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         hipStream_t s = (hipStream_t)stream;
         for (int r = 0; r < reps; ++r) {
             if (stage == KP_STAGE_FWD_FFT) {

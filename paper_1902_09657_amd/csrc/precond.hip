@@ -245,6 +245,7 @@ using namespace kp;
 extern "C" int precond_build(kp_plan_t plan, int kind, float* p, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl || !p) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        require_plan_device(*plan->impl);
         precond_build_impl(*plan->impl, kind, p, (hipStream_t)stream);
     });
 }

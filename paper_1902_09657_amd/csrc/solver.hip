@@ -1354,6 +1354,7 @@ int pdhg_lambda_max(kp_plan_t plan, const float* p, int p_kind, int iters, float
         if (!plan || !plan->impl || !out) fail(KP_ERR_INVALID_ARG, "NULL argument");
         if (iters < 1) fail(KP_ERR_INVALID_ARG, "iters must be >= 1");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         check_p(P, p, p_kind);
         hipStream_t s = (hipStream_t)stream;
         const float* pint = load_p(P, p, p_kind, s);
@@ -1366,6 +1367,7 @@ int pdhg_schedule_params(kp_plan_t plan, const float* p, int p_kind, const kp_pd
     return guarded([&] {
         if (!plan || !plan->impl || !opts || !params) fail(KP_ERR_INVALID_ARG, "NULL argument");
         Plan& P = *plan->impl;
+        require_plan_device(P);
         const kp_pdhg_opts& op = *opts;
         check_p(P, p, p_kind);
         const int K = op.iters;
@@ -1398,6 +1400,7 @@ int l2_dual_cg(kp_plan_t plan, const void* y, const float* p, int p_kind, float 
                void* u_out, double* residual_host, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl || !y || !x_out) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        require_plan_device(*plan->impl);
         l2_dual_cg_impl(*plan->impl, (const float2*)y, p, p_kind, lambda, iters, (float2*)x_out, (float2*)u_out,
                         residual_host, (hipStream_t)stream);
     });
@@ -1407,6 +1410,7 @@ int pdhg_solve(kp_plan_t plan, const void* y, const float* p, int p_kind, const 
                void* u_out, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl || !opts || !y || !x_out) fail(KP_ERR_INVALID_ARG, "NULL argument");
+        require_plan_device(*plan->impl);
         pdhg_solve_impl(*plan->impl, (const float2*)y, p, p_kind, *opts, (float2*)x_out, (float2*)u_out,
                         (hipStream_t)stream);
     });

@@ -369,6 +369,7 @@ int pdhg_unrolled_forward(kp_plan_t plan, const void* y, const float* p, int p_k
                           int ckpt_every, const void* x0, void* x_out, void* ckpt, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
+        require_plan_device(*plan->impl);
         unrolled_forward(*plan->impl, y, p, p_kind, params, K, ckpt_every, x0, x_out, ckpt, (hipStream_t)stream);
     });
 }
@@ -378,6 +379,7 @@ int pdhg_unrolled_backward(kp_plan_t plan, const void* y, const float* p, int p_
                            void* g_y, void* g_x0, void* stream) {
     return guarded([&] {
         if (!plan || !plan->impl) fail(KP_ERR_INVALID_ARG, "plan is NULL");
+        require_plan_device(*plan->impl);
         unrolled_backward(*plan->impl, y, p, p_kind, params, K, ckpt_every, x0, ckpt, g_x, g_params, g_y, g_x0,
                           (hipStream_t)stream);
     });
