@@ -367,6 +367,7 @@ def bench_batched(kp, dev, reps=3):
     t_plan = time.perf_counter() - t0
     fast = all(kp.nufft_batch_info(b, i)["fast"] for i in range(len(sl)))
     tiles = sorted({kp.nufft_batch_info(b, i)["bin_size"] for i in range(len(sl))})
+    spread_tiles = sorted({kp.nufft_batch_info(b, i)["spread_bin_size"] for i in range(len(sl))})
     s = torch.cuda.current_stream()
     e0, e1 = _events()
     xb = kp.pdhg_solve_batch(b, ys, ps, lam=lam, iters=K, lambda_max=lms)    # captures the graph
@@ -394,7 +395,8 @@ def bench_batched(kp, dev, reps=3):
         "workload": "64 uneven 2D radial slices, N in {128,192,256,320}, 32-256 spokes x 2N, 12 coils, "
                     "alpha 1.25, W 4, l2 lambda 1e-3, mc precond, 20 iters",
         "slices": len(sl), "iters": K, "samples_coil_total": MC, "one_launch_per_phase": fast,
-        "tiles": [list(t) for t in tiles], "plan_s_incl_autotune": round(t_plan, 3),
+        "tiles": [list(t) for t in tiles], "spread_tiles": [list(t) for t in spread_tiles],
+        "plan_s_incl_autotune": round(t_plan, 3),
         "batched_ms": round(t_b * 1e3, 3), "plain_ms": round(t_p * 1e3, 3),
         "speedup_vs_plain": round(t_p / t_b, 3),
         "batched_msamples_coil_per_s": round(MC * K / t_b / 1e6, 1),

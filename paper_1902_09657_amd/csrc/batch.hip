@@ -70,13 +70,19 @@ kp_tuning autotune(int ndim, const int64_t* shape, int64_t C, int64_t M, const f
     const int ncg = (int)(C / CG);
     const int chunks[3] = {512, 1024, 2048};
     if (ndim == 2) {
+        // spreading tiles b0 lines x 4 or 2 cells; sort / interpolation tiles
+        // b0 x the default depth
         for (int b0 : {16, 32, 64}) {
             if (b0 * ncg > 256) continue;
-            for (int ch : chunks) {
-                kp_tuning t{};
-                t.bin_size[0] = b0;
-                t.max_chunk = ch;
-                cands.push_back(t);
+            for (int depth : {4, 2}) {
+                for (int ch : chunks) {
+                    kp_tuning t{};
+                    t.bin_size[0] = b0;
+                    t.spread_bin_size[0] = b0;
+                    t.spread_bin_size[1] = depth;
+                    t.max_chunk = ch;
+                    cands.push_back(t);
+                }
             }
         }
     } else {
@@ -177,6 +183,7 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
     std::vector<int64_t> sfA, sfB, saA, saB, sit(n + 1, 0), ssp(n + 1, 0);
     int spread_thr = 64;
     size_t spread_lds = 0;
+    int zm_max = 4;  // register line of the batched spreading kernel: the deepest slice's
     for (int i = 0; i < n; ++i) {
         Plan& P = *B.plans[i];
         float* sig = P.sched.as<float>();
@@ -213,7 +220,11 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
         sit[i + 1] = sit[i] + (P.M * (C / 4) + 255) / 256;
         ssp[i + 1] = ssp[i] + P.nwork;
         spread_thr = std::max(spread_thr, ((spread_threads(2, P.Bs, C) + 63) / 64) * 64);
-        spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C, kZMax));
+        zm_max = std::max(zm_max, spread_zm(2, P.Bs));
+    }
+    for (int i = 0; i < n; ++i) {
+        const Plan& P = *B.plans[i];
+        spread_lds = std::max(spread_lds, spread_lds_bytes(2, P.W, P.Bs, C, zm_max));
     }
     // FFT phases: one persistent launch each over the passes of every slice,
     // sorted by transform length; lines longer than 206 rows use 16-column
@@ -300,7 +311,7 @@ static void capture_fast(Batch& B, const kp_pdhg_opts& op, int p_kind, hipStream
             launch_interp_batch((const InterpArgs*)(d + L.it) + (size_t)k * n, (const int64_t*)(d + L.sit), n, sit[n],
                                 kb, B.cap);
             launch_spread_batch((const SpreadArgs*)(d + L.sp), (const int64_t*)(d + L.ssp), n, ssp[n], spread_thr,
-                                spread_lds, kb, B.cap);
+                                spread_lds, zm_max, kb, B.cap);
             launch_reduce_batch((const SpreadArgs*)(d + L.sp), (const int2*)(d + L.hv), (const int4* const*)(d + L.hl),
                                 nh, B.cap);
             fft_phase(L.aA, L.saA, saA, 0, ph[2]);

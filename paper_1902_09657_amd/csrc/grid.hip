@@ -1060,24 +1060,31 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a, KbParams kb) {
 }
 
 // spreading of many slices in one launch (2D, width 4, coil groups of 4): the
-// work items of slice s are blocks start[s] .. start[s+1]-1
+// work items of slice s are blocks start[s] .. start[s+1]-1; ZM covers the
+// deepest spreading tile of the batch
+template <int ZM>
 __global__ void __launch_bounds__(256) k_spread_batch(const SpreadArgs* __restrict__ args,
                                                       const int64_t* __restrict__ start, int n, KbParams kb) {
     extern __shared__ int smem[];
     const int s = batch_slot(start, n, blockIdx.x);
     const SpreadArgs a = args[s];
-    spread_body<2, 4, 4>(a, kb, blockIdx.x - start[s], smem);
+    spread_body<2, 4, 4, ZM>(a, kb, blockIdx.x - start[s], smem);
 }
 
 void launch_spread_batch(const SpreadArgs* d_args, const int64_t* d_start, int n, int64_t nblk, int threads,
-                         size_t lds, const KbParams& kb, hipStream_t s) {
+                         size_t lds, int zm, const KbParams& kb, hipStream_t s) {
     if (nblk <= 0) return;
     if (nblk > 0x7fffffff) fail(KP_ERR_UNSUPPORTED, "batched spreading grid too large");
+    if (zm != 4 && zm != kZMax) fail(KP_ERR_UNSUPPORTED, "batched spreading: register line must be 4 or 8 cells");
+    const void* fn = zm == 4 ? (const void*)k_spread_batch<4> : (const void*)k_spread_batch<kZMax>;
     if (lds > 65536) {
-        (void)hipFuncSetAttribute((const void*)k_spread_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     }
-    hipLaunchKernelGGL(k_spread_batch, dim3((unsigned)nblk), dim3(threads), lds, s, d_args, d_start, n, kb);
+    if (zm == 4)
+        hipLaunchKernelGGL(k_spread_batch<4>, dim3((unsigned)nblk), dim3(threads), lds, s, d_args, d_start, n, kb);
+    else
+        hipLaunchKernelGGL(k_spread_batch<kZMax>, dim3((unsigned)nblk), dim3(threads), lds, s, d_args, d_start, n, kb);
     KP_LAUNCH_CHECK();
 }
 

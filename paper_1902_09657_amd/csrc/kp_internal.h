@@ -314,7 +314,7 @@ void launch_fft_batch_mixed(const FftPass* d_passes, const int64_t* d_blk_start,
 void launch_interp_batch(const InterpArgs* d_args, const int64_t* d_start, int n, int64_t nblk, const KbParams& kb,
                          hipStream_t s);
 void launch_spread_batch(const SpreadArgs* d_args, const int64_t* d_start, int n, int64_t nblk, int threads,
-                         size_t lds, const KbParams& kb, hipStream_t s);
+                         size_t lds, int zm, const KbParams& kb, hipStream_t s);
 void launch_reduce_batch(const SpreadArgs* d_args, const int2* d_hv, const int4* const* d_lists, int nh,
                          hipStream_t s);
 void pdhg_setup(Plan& P, const float2* y, const float* p, int p_kind, const kp_pdhg_opts& op, hipStream_t s);

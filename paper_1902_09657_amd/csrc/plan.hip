@@ -560,9 +560,9 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
 
     // tiles: the last axis at most kZMax cells (one register line per owner
     // thread); 3D leading axes 8 x 8, 2D leading axis up to 64 lines, within
-    // 256 threads; every B_a divides G_a and leaves G_a >= B_a + W - 1.  In
-    // 3D the spreading tiles are 4 cells deep along the last axis by default
-    // (a 4-cell register line wastes fewer zero-weight taps), the sort tiles 8.
+    // 256 threads; every B_a divides G_a and leaves G_a >= B_a + W - 1.  The
+    // spreading tiles are 4 cells deep along the last axis by default (a
+    // 4-cell register line wastes fewer zero-weight taps), the sort tiles 8.
     const int C = (int)ncoils;
     const int CG = C % 4 == 0 ? 4 : (C % 2 == 0 ? 2 : 1);
     const int ncg = C / CG;
@@ -590,7 +590,7 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
             bs = tuning->spread_bin_size[ax];
         else if (tuning && tuning->bin_size[ax] > 0)
             bs = b;
-        else if (ndim == 3 && ax == ndim - 1)
+        else if (ax == ndim - 1)
             bs = pick_bin(P->G[ax], std::min(4, cap));
         else
             bs = b;

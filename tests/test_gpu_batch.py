@@ -172,6 +172,8 @@ def test_batch_autotune_cached_and_valid():
     assert t1 == t2
     assert 160 % t1["bin_size"][0] == 0 and t1["bin_size"][0] * 3 <= 256
     assert t1["max_chunk"] in (512, 1024, 2048)
+    # spreading tiles: the sort tile's lines, 4 or 2 cells deep
+    assert t1["spread_bin_size"][0] == t1["bin_size"][0] and t1["spread_bin_size"][1] in (2, 4)
 
 
 def test_batch_invalid():
