@@ -231,9 +231,17 @@ __global__ void k_iota(int32_t* v, int64_t n) {
     if (i < n) v[i] = (int32_t)i;
 }
 
-__global__ void k_count_keys(const uint32_t* key, int64_t n, int* cnt) {
+// Offsets of every key in a sorted key array: off[t] = number of keys < t
+// for t = 0 .. nkeys.  Thread i (0 <= i <= n) writes the keys in
+// (key[i-1], key[i]] (from 0 for i = 0, up to nkeys for i = n), so no two
+// threads write one entry and no atomics are needed (a count with atomics
+// serialises on the long runs of equal keys).
+__global__ void k_sorted_offsets(const uint32_t* key, int64_t n, int64_t nkeys, int* off) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[key[i]], 1);
+    if (i > n) return;
+    const int64_t lo = i == 0 ? 0 : (int64_t)key[i - 1] + 1;
+    const int64_t hi = i == n ? nkeys : (int64_t)key[i];
+    for (int64_t t = lo; t <= hi; ++t) off[t] = (int)i;
 }
 
 __global__ void k_gather_coords(const float* g, const int32_t* perm, int64_t M, int d, float* gs) {
@@ -639,10 +647,9 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_LAUNCH_CHECK();
     radix_sort_pairs(keys.as<uint32_t>(), P->perm.as<int32_t>(), M, (uint32_t)(P->nbins - 1), s);
     P->bin_off.alloc(sizeof(int) * (P->nbins + 1));
-    KP_HIP(hipMemsetAsync(P->bin_off.p, 0, sizeof(int) * (P->nbins + 1), s));
-    hipLaunchKernelGGL(k_count_keys, dim3(nblk(M)), dim3(256), 0, s, keys.as<uint32_t>(), M, P->bin_off.as<int>());
+    hipLaunchKernelGGL(k_sorted_offsets, dim3(nblk(M + 1)), dim3(256), 0, s, keys.as<uint32_t>(), M, P->nbins,
+                       P->bin_off.as<int>());
     KP_LAUNCH_CHECK();
-    scan_exclusive(P->bin_off.as<int>(), P->bin_off.as<int>(), P->nbins + 1, s);
     P->g_sorted.alloc(sizeof(float) * M * d);
     hipLaunchKernelGGL(k_gather_coords, dim3(nblk(M)), dim3(256), 0, s, P->g_orig.as<float>(),
                        P->perm.as<int32_t>(), M, d, P->g_sorted.as<float>());
@@ -671,11 +678,9 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
     KP_LAUNCH_CHECK();
     radix_sort_pairs(tkeys.as<uint32_t>(), P->touch.as<int32_t>(), ntouch, (uint32_t)(P->nstiles - 1), s);
     P->touch_off.alloc(sizeof(int) * (P->nstiles + 1));
-    KP_HIP(hipMemsetAsync(P->touch_off.p, 0, sizeof(int) * (P->nstiles + 1), s));
-    hipLaunchKernelGGL(k_count_keys, dim3(nblk(ntouch)), dim3(256), 0, s, tkeys.as<uint32_t>(), (int64_t)ntouch,
-                       P->touch_off.as<int>());
+    hipLaunchKernelGGL(k_sorted_offsets, dim3(nblk((int64_t)ntouch + 1)), dim3(256), 0, s, tkeys.as<uint32_t>(),
+                       (int64_t)ntouch, P->nstiles, P->touch_off.as<int>());
     KP_LAUNCH_CHECK();
-    scan_exclusive(P->touch_off.as<int>(), P->touch_off.as<int>(), P->nstiles + 1, s);
 
     // ---- spreading work items (host): heavy tiles split, largest work first
     std::vector<int> toff(P->nstiles + 1);
