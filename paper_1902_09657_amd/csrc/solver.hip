@@ -593,6 +593,31 @@ __device__ __forceinline__ void dwt3_load(const Dwt3Args& a, float2* buf, Pos po
     }
 }
 
+// Brick load of the analysis: as dwt3_load, but a thread owns two adjacent
+// columns (u1, u2), (u1, u2 + 1) with u2 even and reads both with one 16-byte
+// load per row.  Along axis 2 the loaded rows 2 k B + u wrap by the even
+// extent n, so an even position stays even and its pair never straddles the
+// wrap; every stride of the image is even, so those loads are 16-byte aligned.
+template <class K, typename Pos>
+__device__ __forceinline__ void dwt3_load_pairs(const Dwt3Args& a, float2* buf, Pos pos) {
+    static_assert(K::IN2 % 2 == 0, "pairs along axis 2");
+    constexpr int HP = K::IN2 / 2, NPAIR = K::IN1 * HP;
+    static_assert(NPAIR <= 256, "one pair of columns per thread");
+    const int tid = threadIdx.x;
+    if (tid >= NPAIR) return;
+    const int u1 = tid / HP, u2 = 2 * (tid - u1 * HP);
+    const float2* src = a.in + __umul24(pos(1, u1), a.S1) + pos(2, u2);
+    float4 v[K::IN0];
+#pragma unroll
+    for (int u0 = 0; u0 < K::IN0; ++u0) v[u0] = *reinterpret_cast<const float4*>(src + __umul24(pos(0, u0), a.S0));
+#pragma unroll
+    for (int u0 = 0; u0 < K::IN0; ++u0) {
+        float2* d = buf + (u0 * K::IN1 + u1) * K::P2 + u2;
+        d[0] = make_float2(v[u0].x, v[u0].y);
+        d[1] = make_float2(v[u0].z, v[u0].w);
+    }
+}
+
 // analysis of one line held in registers: outputs r < B low band, r >= B high
 template <int B, int IN>
 __device__ __forceinline__ void dwt3_fwd_line(const float2* v, float2* o) {
@@ -644,7 +669,7 @@ __global__ void __launch_bounds__(256) k_dwt3_analysis(Dwt3Args a) {
     // input rows 2 k B .. 2 k B + 2B + 5 of every axis, periodic: one wrap
     // needs one subtraction when the extent is at least the loaded extent, a
     // loop otherwise (deep levels of small images)
-    dwt3_load<K>(a, buf, [&](int ax, int u) {
+    dwt3_load_pairs<K>(a, buf, [&](int ax, int u) {
         constexpr int Bs[3] = {B0, B1, B2}, INs[3] = {IN0, IN1, IN2};
         const int n = a.n[ax];
         int sidx = 2 * q[ax] * Bs[ax] + u;
