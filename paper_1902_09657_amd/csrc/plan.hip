@@ -742,14 +742,15 @@ Plan* create_plan(int ndim, const int64_t* shape, int64_t ncoils, int64_t nsampl
         }
     }
     // Built-in split size: 1024 entries when the plan has work for thousands
-    // of such items, halved down to one chunk otherwise.  A small plan (a 2D
-    // slice) has too few tiles to fill the GPU, so its time is the longest
-    // work item's chain of chunks; a large one (3D) is throughput bound, where
-    // fewer, longer items cost fewer partial tiles.
+    // of such items, halved down to half a chunk otherwise.  A small plan (a
+    // 2D slice) has too few tiles to fill the GPU, so its time is the longest
+    // work item's gathers, and in the dense k-space centre all of an item's
+    // entries reach the same few lines of its tile; a large one (3D) is
+    // throughput bound, where fewer, longer items cost fewer partial tiles.
     if (max_chunk == 0) {
         const int64_t entries = toff[P->nstiles];
         max_chunk = 1024;
-        while (max_chunk > kSpreadChunk && entries < (int64_t)4096 * max_chunk) max_chunk /= 2;
+        while (max_chunk > kSpreadChunk / 2 && entries < (int64_t)4096 * max_chunk) max_chunk /= 2;
     }
     P->max_chunk = max_chunk;
     std::vector<int4> heavy_items, light_items;
