@@ -96,6 +96,33 @@ def test_grid_coords_and_sort_bit_exact(shape, C, M, alpha, W):
     plan.close()
 
 
+@pytest.mark.parametrize("where", ["centre", "corner", "two", "one"])
+def test_sort_offsets_degenerate_trajectories(where):
+    """Bin and tile offsets when every sample falls in one or two bins
+    (long runs of equal keys, empty leading and trailing bins): bit-exact."""
+    kp = _kp()
+    shape = (24, 40, 32)
+    M = {"centre": 3000, "corner": 2000, "two": 2500, "one": 1}[where]
+    k = np.zeros((M, 3), np.float32)
+    if where == "corner":
+        k[:] = np.float32(-np.pi)
+    elif where == "two":
+        k[M // 2:] = np.float32(2.5)
+    print("degenerate sort", where, flush=True)
+    plan = _plan(kp, k, shape, None, 1.25, 4)
+    info = plan.info()
+    G = onufft.grid_shape(shape, 1.25)
+    g_or = onufft.canonical_coords(k, G)
+    perm_o, off_o = onufft.sort_by_bin(g_or, G, info["bin_size"])
+    perm, boff, toff, touch = [t.cpu().numpy() for t in plan.sort()]
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(boff, off_o)
+    toff_o, touch_o = onufft.tile_touch_lists(g_or[perm_o], G, info["spread_bin_size"], 4)
+    assert np.array_equal(toff, toff_o)
+    assert np.array_equal(touch, touch_o)
+    plan.close()
+
+
 NSPECIAL = 8   # synth.random_coords puts its special points first
 
 
