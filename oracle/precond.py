@@ -30,11 +30,25 @@ evaluates them exactly (NDFT on the 2N image), `efficient_nufft` with the
 gridding NUFFT on the 2N image using the plan's alpha and W.  SC is the same
 build with C = 1 and s = 1, where r is the separable triangle prod(N_a - |k_a|).
 
+Pipe-Menon density compensation (Experiments: the first of the three k-space
+preconditioners compared with PDHG, from Pipe and Menon's gridding work):
+the fixed-point iteration w <- w / |(C * C * w)(x_i)| from w = 1, where the
+convolution with the gridding kernel C is evaluated by spreading w onto the
+oversampled grid and interpolating back at the samples (the NUFFT's own
+kernel, alpha and W), `pipe_menon_dcf`.  Readings (the paper gives no
+details): 30 iterations, the plan's kernel and grid, one weight per sample
+shared by every coil; its scale is immaterial to PDHG, whose step sizes come
+from lambda_max(P A A^H).
+
 Pins: definition vs efficient_exact (1e-10); SC closed form vs definition;
 Cartesian full sampling gives p = 1 (SC, and MC with unit sum-of-squares
 maps); MC at C = 1, s = 1 equals SC; p > 0 and invariance to a global map
 phase; efficient_nufft vs definition within the NUFFT error
-(tests/test_oracle_solver.py).
+(tests/test_oracle_solver.py).  DCF: duplicating every sample halves every
+weight; a single sample's weight is 1 / prod_a sum_t C(u_at)^2 of the kernel
+taps; the weights of a fully sampled Cartesian grid on the grid points are
+equal; on a 2D radial trajectory they grow like |k| (log-log slope 1) in the
+mid range.
 """
 from __future__ import annotations
 
@@ -138,3 +152,15 @@ def efficient_nufft(maps, coords, shape, alpha, width):
         s = op.forward(v)[0] * math.sqrt(2.0 ** d)
         out.append(np.real(s) / nrm[c])
     return 1.0 / np.stack(out)
+
+
+def pipe_menon_dcf(coords, shape, alpha, width, iters=30):
+    """Pipe-Menon density compensation weights, shape (M,): w <- w / |G G^T w|
+    with G the gridding interpolation (kernel taps onto the oversampled grid),
+    `iters` times from w = 1."""
+    op = Nufft(coords, shape, None, alpha, width)
+    w = np.ones(op.M)
+    for _ in range(iters):
+        v = op.interp(op.spread(w.astype(np.complex128)))
+        w = w / np.abs(v)
+    return w

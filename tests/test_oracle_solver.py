@@ -77,6 +77,51 @@ def test_precond_nufft_build_within_nufft_error():
     assert np.max(np.abs(pn4 - pd) / pd) < 5e-2
 
 
+def test_dcf_duplicated_samples_halve():
+    rng = np.random.default_rng(8)
+    k = synth.random_coords(200, 2, rng)
+    w1 = precond.pipe_menon_dcf(k, (12, 16), 1.25, 4)
+    w2 = precond.pipe_menon_dcf(np.concatenate([k, k]), (12, 16), 1.25, 4)
+    np.testing.assert_allclose(2 * w2[:200], w1, rtol=1e-12)
+    np.testing.assert_allclose(2 * w2[200:], w1, rtol=1e-12)
+
+
+@pytest.mark.parametrize("kk", [(0.3, -1.1), (-math.pi, 2.0), (1.7, 0.0, -0.4)])
+def test_dcf_single_sample_from_kernel_taps(kk):
+    from oracle import kb as okb
+    k = np.array([kk], np.float32)
+    shape = (16,) * len(kk)
+    alpha, W = 1.25, 4
+    G = nufft.grid_shape(shape, alpha)
+    g = nufft.canonical_coords(k, G)[0].astype(np.float64)
+    beta = okb.kb_beta(alpha, W)
+    v = 1.0
+    for a in range(len(kk)):
+        j = np.floor(g[a]) - W // 2 + 1 + np.arange(W)
+        v *= float(np.sum(okb.kb_kernel(g[a] - j, W, beta) ** 2))
+    w = precond.pipe_menon_dcf(k, shape, alpha, W)
+    np.testing.assert_allclose(w, [1.0 / v], rtol=1e-12)
+
+
+def test_dcf_equal_on_a_cartesian_grid():
+    shape = (16, 16)
+    w = precond.pipe_menon_dcf(_cartesian(shape), shape, 2.0, 4)   # samples on grid points
+    assert (w.max() - w.min()) / w.mean() < 1e-2
+
+
+def test_dcf_radial_grows_like_radius():
+    k = synth.radial_2d(256, 128)
+    w = precond.pipe_menon_dcf(k, (64, 64), 1.25, 4)
+    r = np.linalg.norm(k.astype(np.float64), axis=1)
+    m = (r > 0.25 * math.pi) & (r < 0.75 * math.pi)
+    slope = np.polyfit(np.log(r[m]), np.log(w[m]), 1)[0]
+    assert abs(slope - 1.0) < 0.05, slope
+    # converged: the gridding kernel's self-convolution of w is ~1 at the samples
+    op = nufft.Nufft(k, (64, 64), None, 1.25, 4)
+    v = np.abs(op.interp(op.spread(w.astype(np.complex128))))
+    assert np.median(np.abs(v - 1.0)) < 1e-2
+
+
 # ---------------------------------------------------------------- wavelet
 def test_db4_defining_identity():
     h = wavelet.db4_filter()
