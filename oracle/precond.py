@@ -37,8 +37,11 @@ convolution with the gridding kernel C is evaluated by spreading w onto the
 oversampled grid and interpolating back at the samples (the NUFFT's own
 kernel, alpha and W), `pipe_menon_dcf`.  Readings (the paper gives no
 details): 30 iterations, the plan's kernel and grid, one weight per sample
-shared by every coil; its scale is immaterial to PDHG, whose step sizes come
-from lambda_max(P A A^H).
+shared by every coil.  The raw weights have an arbitrary scale, and with the
+dual step fixed (sigma0 = 1) the primal step tau = 1/lambda_max(P A A^H)
+carries it into the proximal threshold; `dcf_preconditioner` therefore scales
+them so that lambda_max(P A A^H) = 1 (power method, 30 iterations), the value
+the l2-optimised preconditioners are designed to approach.
 
 Pins: definition vs efficient_exact (1e-10); SC closed form vs definition;
 Cartesian full sampling gives p = 1 (SC, and MC with unit sum-of-squares
@@ -164,3 +167,11 @@ def pipe_menon_dcf(coords, shape, alpha, width, iters=30):
         v = op.interp(op.spread(w.astype(np.complex128)))
         w = w / np.abs(v)
     return w
+
+
+def dcf_preconditioner(coords, shape, maps, alpha, width, iters=30, power_iters=30):
+    """Pipe-Menon weights scaled to lambda_max(P A A^H) = 1, shape (M,)."""
+    from .pdhg import power_method
+    w = pipe_menon_dcf(coords, shape, alpha, width, iters)
+    op = Nufft(coords, shape, maps, alpha, width)
+    return w / power_method(op.forward, op.adjoint, w, shape, power_iters)

@@ -103,6 +103,22 @@ def test_dcf_single_sample_from_kernel_taps(kk):
     np.testing.assert_allclose(w, [1.0 / v], rtol=1e-12)
 
 
+def test_dcf_preconditioner_has_unit_lambda_max():
+    from oracle import pdhg as opdhg
+    rng = np.random.default_rng(9)
+    shape = (12, 16)
+    k = synth.random_coords(400, 2, rng)
+    maps = synth.coil_maps(shape, 3, rng)
+    p = precond.dcf_preconditioner(k, shape, maps, 1.25, 4)
+    A = ndft.matrix(maps, k, shape)                       # dense (CM, N)
+    Pb = np.tile(p, 3)                                    # one weight per sample, every coil
+    lam = np.linalg.eigvalsh((A.conj().T * Pb) @ A).max()  # lambda_max(A^H P A) = lambda_max(P A A^H)
+    # the power method on the gridding NUFFT: within its error of the exact A
+    assert abs(lam - 1.0) < 2e-2, lam
+    op = nufft.Nufft(k, shape, maps, 1.25, 4)
+    assert abs(opdhg.power_method(op.forward, op.adjoint, p, shape, 30) - 1.0) < 1e-6
+
+
 def test_dcf_equal_on_a_cartesian_grid():
     shape = (16, 16)
     w = precond.pipe_menon_dcf(_cartesian(shape), shape, 2.0, 4)   # samples on grid points
