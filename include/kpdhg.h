@@ -51,7 +51,7 @@ enum {
     KP_ERR_HIP = -4           /* a HIP runtime call or kernel failed       */
 };
 
-enum { KP_PRECOND_NONE = 0, KP_PRECOND_SC = 1, KP_PRECOND_MC = 2 };
+enum { KP_PRECOND_NONE = 0, KP_PRECOND_SC = 1, KP_PRECOND_MC = 2, KP_PRECOND_DCF = 3 };
 enum { KP_REG_L2 = 0, KP_REG_L1_WAVELET = 1, KP_REG_TV = 2 };
 
 /* Kernel tiling.  Zeros select the built-in choice for the shape.
@@ -160,6 +160,15 @@ int nufft_adjoint(kp_plan_t plan, const void* y, void* x, void* stream);
  * their product, p = 1/Re(.).
  *   kind KP_PRECOND_SC: Eq. sc_precond (coil maps ignored), p float [M]
  *   kind KP_PRECOND_MC: Eq. mc_precond, p float [C][M]
+ *   kind KP_PRECOND_DCF: the Pipe-Menon density compensation factor, the
+ *     first of the three k-space preconditioners the Experiments compare:
+ *     w <- w / |G G^T w| from w = 1, 30 times, G the plan's gridding
+ *     interpolation (its kernel and oversampled grid, no FFT); p float [M]
+ *     (one weight per sample; pass it to the solver calls as p_kind
+ *     KP_PRECOND_SC), scaled so that lambda_max(P A A^H) = 1 (power method,
+ *     30 iterations): with the fixed dual step the primal step 1/lambda_max
+ *     would otherwise carry the weights' arbitrary scale into the proximal
+ *     threshold.  Uses the plan's internal buffers.
  * Caller sample order.  Allocates and frees scratch; synchronises. */
 int precond_build(kp_plan_t plan, int kind, float* p, void* stream);
 

@@ -12,13 +12,13 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVELET, KP_REG_L2, KP_REG_TV,
+from ._lib import (KP_PRECOND_DCF, KP_PRECOND_MC, KP_PRECOND_NONE, KP_PRECOND_SC, KP_REG_L1_WAVELET, KP_REG_L2, KP_REG_TV,
                    KpError, PdhgOpts, PlanInfo, Tuning)
 
 __all__ = [
     "Plan", "nufft_plan", "nufft_forward", "nufft_forward_noalloc", "nufft_adjoint", "precond_build", "pdhg_lambda_max",
     "pdhg_solve", "l2_dual_cg", "nufft_destroy", "nufft_autotune", "Batch", "nufft_plan_batch", "nufft_batch_info",
-    "pdhg_solve_batch", "nufft_batch_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC",
+    "pdhg_solve_batch", "nufft_batch_destroy", "KpError", "KP_PRECOND_NONE", "KP_PRECOND_SC", "KP_PRECOND_MC", "KP_PRECOND_DCF",
     "KP_REG_L2", "KP_REG_L1_WAVELET", "KP_REG_TV",
 ]
 
@@ -186,7 +186,8 @@ def nufft_adjoint(plan: Plan, y, out=None):
 
 
 def precond_build(plan: Plan, kind):
-    n = (plan.nsamples,) if kind == KP_PRECOND_SC else (plan.ncoils, plan.nsamples)
+    """p for kind SC or DCF: float32 [M]; MC: [C, M] (caller sample order)."""
+    n = (plan.nsamples,) if kind in (KP_PRECOND_SC, KP_PRECOND_DCF) else (plan.ncoils, plan.nsamples)
     p = torch.empty(n, dtype=torch.float32, device=plan.device)
     _lib.check(_lib.load().precond_build(plan.handle, int(kind), _ptr(p), _stream()))
     return p

@@ -18,7 +18,7 @@ KP_ERR_INVALID_ARG = -1
 KP_ERR_UNSUPPORTED = -2
 KP_ERR_OOM = -3
 KP_ERR_HIP = -4
-KP_PRECOND_NONE, KP_PRECOND_SC, KP_PRECOND_MC = 0, 1, 2
+KP_PRECOND_NONE, KP_PRECOND_SC, KP_PRECOND_MC, KP_PRECOND_DCF = 0, 1, 2, 3
 KP_REG_L2, KP_REG_L1_WAVELET, KP_REG_TV = 0, 1, 2
 
 # every symbol the header declares

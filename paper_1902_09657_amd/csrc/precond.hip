@@ -159,8 +159,64 @@ static void fft_image(const float2* in, float2* out, float2* tmp, int d, const i
     }
 }
 
+// ---- Pipe-Menon density compensation (Experiments: the first of the three
+// k-space preconditioners compared with PDHG): w <- w / |G G^T w| from w = 1,
+// with G the plan's gridding interpolation (the spreading and interpolation
+// kernels on one channel, no FFT), kDcfIters times; one weight per sample.
+// The raw weights have an arbitrary scale, which the fixed dual step would
+// pass on to the proximal threshold through tau = 1/lambda_max(P A A^H), so
+// they are scaled to lambda_max(P A A^H) = 1 (power method, 30 iterations as
+// for the solver), the value the l2-optimised preconditioners approach.
+constexpr int kDcfIters = 30;
+constexpr int kDcfPowerIters = 30;
+
+__global__ void k_dcf_update(float2* w, const float2* v, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const float2 t = v[i];
+    w[i] = make_float2(w[i].x / sqrtf(t.x * t.x + t.y * t.y), 0.f);
+}
+
+__global__ void k_real_part(const float2* w, int64_t M, float* q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) q[i] = w[i].x;
+}
+
+__global__ void k_divide_by(float* q, int64_t M, const float* lam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) q[i] = q[i] / lam[0];
+}
+
+static void dcf_build(Plan& P, float* p_out, hipStream_t s) {
+    float2* w = P.kint.as<float2>();
+    float2* v = P.kint3.as<float2>();
+    hipLaunchKernelGGL(k_ones_k, dim3(nblk(P.M)), dim3(256), 0, s, w, P.M);
+    KP_LAUNCH_CHECK();
+    for (int it = 0; it < kDcfIters; ++it) {
+        const float2* g = spread_to_grid(P, w, 1, s);
+        InterpArgs ia{};
+        ia.mode = IO_INTERNAL;
+        ia.out = v;
+        ia.C = 1;
+        interp(P, g, ia, s);
+        hipLaunchKernelGGL(k_dcf_update, dim3(nblk(P.M)), dim3(256), 0, s, w, v, P.M);
+        KP_LAUNCH_CHECK();
+    }
+    float* q = P.pint.as<float>();
+    hipLaunchKernelGGL(k_real_part, dim3(nblk(P.M)), dim3(256), 0, s, w, P.M, q);
+    KP_LAUNCH_CHECK();
+    DevBuf lam;
+    lam.alloc(sizeof(float));
+    power_method(P, q, 0, kDcfPowerIters, lam.as<float>(), s);
+    hipLaunchKernelGGL(k_divide_by, dim3(nblk(P.M)), dim3(256), 0, s, q, P.M, lam.as<float>());
+    KP_LAUNCH_CHECK();
+    permute_p_to_caller(q, p_out, P.perm.as<int32_t>(), P.M, 1, false, s);
+    KP_HIP(hipStreamSynchronize(s));
+}
+
 void precond_build_impl(Plan& P, int kind, float* p_out, hipStream_t s) {
-    if (kind != KP_PRECOND_SC && kind != KP_PRECOND_MC) fail(KP_ERR_INVALID_ARG, "kind must be SC or MC");
+    if (kind == KP_PRECOND_DCF) return dcf_build(P, p_out, s);
+    if (kind != KP_PRECOND_SC && kind != KP_PRECOND_MC) fail(KP_ERR_INVALID_ARG, "kind must be SC, MC or DCF");
     const int d = P.d;
     const bool mc = kind == KP_PRECOND_MC;
     const int Cp = mc ? (int)P.C : 1;

@@ -66,6 +66,14 @@ def test_precond_parity(shape, C, M, alpha, W, kind):
         p_mc = kp.precond_build(plan, kp.KP_PRECOND_MC).cpu().numpy()
         o_mc = oprecond.efficient_nufft(maps, k, shape, alpha, W)
         assert rel(p_mc, o_mc) < 1e-4
+    # Pipe-Menon density compensation on the plan's own gridding kernel,
+    # scaled to lambda_max(P A A^H) = 1
+    p_dcf = kp.precond_build(plan, kp.KP_PRECOND_DCF).cpu().numpy()
+    o_dcf = oprecond.dcf_preconditioner(k, shape, maps, alpha, W)
+    assert p_dcf.shape == (k.shape[0],)
+    assert rel(p_dcf, o_dcf) < 1e-4
+    assert np.max(np.abs(p_dcf - o_dcf) / o_dcf) < 1e-3
+    assert np.all(p_dcf > 0)
     plan.close()
 
 
@@ -106,6 +114,9 @@ def test_lambda_max_parity(pk):
 
 
 SOLVE_CASES = [
+    # the Pipe-Menon density compensation as the k-space preconditioner
+    ((32, 32), 1, 2048, 2.0, 4, "l2", 1e-3, "dcf", 20, 4),
+    ((16, 16, 24), 3, 4000, 1.25, 4, "l1wav", 5e-3, "dcf", 8, 2),
     # shape, C, M, alpha, W, reg, lam, precond, iters, levels
     ((32, 48), 4, 3000, 1.25, 4, "l2", 1e-3, "mc", 20, 4),
     ((32, 32), 1, 2048, 2.0, 4, "l2", 1e-3, "sc", 20, 4),
@@ -145,6 +156,8 @@ def test_pdhg_parity(shape, C, M, alpha, W, reg, lam, pk, iters, levels):
         p = None
     elif pk == "sc":
         p = oprecond.efficient_nufft(None, k, shape, alpha, W)[0]
+    elif pk == "dcf":
+        p = oprecond.dcf_preconditioner(k, shape, maps, alpha, W)
     else:
         p = oprecond.efficient_nufft(maps, k, shape, alpha, W)
     pt = None if p is None else dev(p, torch.float32)
