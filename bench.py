@@ -299,7 +299,8 @@ def gpu_clock():
 
 
 def precond_comparison_3d(kp, plan, y, p_mc, cfg, lmax_mc, dev):
-    """P = I vs SC vs MC on the timed 3D UTE workload (l1-db4, lambda 5e-3):
+    """P = I vs SC vs MC vs the Pipe-Menon DCF on the timed 3D UTE workload
+    (l1-db4, lambda 5e-3):
     the normalised objective gap (f_k - f*) / (f_0 - f*) at k = 5, 10, 20, 30,
     f* the least objective of 300 MC-preconditioned iterations, and the time
     per iteration of each preconditioner (lambda_max by 30 power iterations
@@ -307,9 +308,15 @@ def precond_comparison_3d(kp, plan, y, p_mc, cfg, lmax_mc, dev):
     import torch
     s = torch.cuda.current_stream()
     e0, e1 = _events()
-    ps = {"none": None, "sc": kp.precond_build(plan, kp.KP_PRECOND_SC), "mc": p_mc}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p_dcf = kp.precond_build(plan, kp.KP_PRECOND_DCF)
+    torch.cuda.synchronize()
+    dcf_s = time.perf_counter() - t0
+    ps = {"none": None, "sc": kp.precond_build(plan, kp.KP_PRECOND_SC), "mc": p_mc, "dcf": p_dcf}
     lm = {"none": float(kp.pdhg_lambda_max(plan, None, 30).item()),
-          "sc": float(kp.pdhg_lambda_max(plan, ps["sc"], 30).item()), "mc": lmax_mc}
+          "sc": float(kp.pdhg_lambda_max(plan, ps["sc"], 30).item()), "mc": lmax_mc,
+          "dcf": float(kp.pdhg_lambda_max(plan, ps["dcf"], 30).item())}
     kw = dict(reg=cfg.reg, lam=cfg.lam, wavelet_levels=4)
     _, ref = kp.pdhg_solve(plan, y, p_mc, iters=300, lambda_max=lm["mc"], objective=True, **kw)
     fstar = min(ref)
@@ -325,7 +332,8 @@ def precond_comparison_3d(kp, plan, y, p_mc, cfg, lmax_mc, dev):
         comp[name] = {"gap_at": {str(i): float("%.4g" % gap[i]) for i in (5, 10, 20, 30)},
                       "ms_per_iter": round(e0.elapsed_time(e1) / 30, 4), "lambda_max": round(lm[name], 6)}
     return {"workload": cfg.name + ", l1-db4 lambda 5e-3, 30 iterations",
-            "reference": "f* = least objective of 300 MC-preconditioned iterations", "gap": comp}
+            "reference": "f* = least objective of 300 MC-preconditioned iterations", "gap": comp,
+            "dcf_build_s": round(dcf_s, 4)}
 
 
 def bench_batched(kp, dev, reps=3):
@@ -522,7 +530,8 @@ def bench_context(kp, dev):
         torch.from_numpy(w.astype(np.complex64)).to(dev)
     hi.close()
     plan = kp.nufft_plan(kt, cfg.shape, mt, oversamp=cfg.alpha, kb_width=cfg.width)
-    ps = {"none": None, "sc": kp.precond_build(plan, kp.KP_PRECOND_SC), "mc": kp.precond_build(plan, kp.KP_PRECOND_MC)}
+    ps = {"none": None, "sc": kp.precond_build(plan, kp.KP_PRECOND_SC), "mc": kp.precond_build(plan, kp.KP_PRECOND_MC),
+          "dcf": kp.precond_build(plan, kp.KP_PRECOND_DCF)}
     _, ref = kp.pdhg_solve(plan, y, ps["mc"], reg=cfg.reg, lam=cfg.lam, iters=300, wavelet_levels=4, objective=True)
     fstar = min(ref)
     s = torch.cuda.current_stream()
