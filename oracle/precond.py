@@ -157,14 +157,24 @@ def efficient_nufft(maps, coords, shape, alpha, width):
     return 1.0 / np.stack(out)
 
 
-def pipe_menon_dcf(coords, shape, alpha, width, iters=30):
+def pipe_menon_dcf(coords, shape, alpha, width, iters=30, op=None):
     """Pipe-Menon density compensation weights, shape (M,): w <- w / |G G^T w|
     with G the gridding interpolation (kernel taps onto the oversampled grid),
-    `iters` times from w = 1."""
-    op = Nufft(coords, shape, None, alpha, width)
+    `iters` times from w = 1.  `op`: an oracle Nufft already built on the same
+    coordinates, shape, alpha and width (its taps are reused; maps play no
+    part).  The weights are real, so spreading and interpolation run on real
+    arrays."""
+    if op is None:
+        op = Nufft(coords, shape, None, alpha, width)
+    size = int(np.prod(op.G))
     w = np.ones(op.M)
     for _ in range(iters):
-        v = op.interp(op.spread(w.astype(np.complex128)))
+        grid = np.zeros(size)
+        for flat, t in op._taps:
+            grid += np.bincount(flat, weights=t * w, minlength=size)
+        v = np.zeros(op.M)
+        for flat, t in op._taps:
+            v += t * grid[flat]
         w = w / np.abs(v)
     return w
 

@@ -212,6 +212,22 @@ def ute2(ute):
     plan2.close()
 
 
+def test_3d_ute_dcf_full(ute):
+    """The Pipe-Menon weights of the timed plan (2.56 M samples, 30 fixed-point
+    iterations): the GPU's scaled weights are the oracle's raw weights times
+    one constant (1 / lambda_max), sample by sample."""
+    kp, cfg, x, maps, k, w, op, plan = ute
+    print("3D UTE DCF", flush=True)
+    p = kp.precond_build(plan, kp.KP_PRECOND_DCF).cpu().numpy().astype(np.float64)
+    wo = oprecond.pipe_menon_dcf(k, cfg.shape, cfg.alpha, cfg.width, op=op)
+    ratio = p / wo
+    c = float(np.median(ratio))
+    print("3D UTE DCF scale", c, "max dev", float(np.max(np.abs(ratio / c - 1.0))), flush=True)
+    assert np.all(p > 0)
+    assert rel(p / c, wo) < 1e-4
+    assert np.max(np.abs(ratio / c - 1.0)) < 1e-3
+
+
 def test_3d_ute_mc_precond_full(ute2):
     kp, cfg, x, m2, k, w, op2, plan2, p_o, lmax_o = ute2
     p_g = kp.precond_build(plan2, kp.KP_PRECOND_MC).cpu().numpy()
