@@ -90,6 +90,7 @@ int main() {
     expect(nufft_forward(nullptr, p, p, nullptr), KP_ERR_INVALID_ARG, "forward NULL plan");
     expect(nufft_adjoint(nullptr, p, p, nullptr), KP_ERR_INVALID_ARG, "adjoint NULL plan");
     expect(precond_build(nullptr, KP_PRECOND_SC, p, nullptr), KP_ERR_INVALID_ARG, "precond NULL plan");
+    expect(precond_build(nullptr, KP_PRECOND_DCF, p, nullptr), KP_ERR_INVALID_ARG, "DCF precond NULL plan");
     expect(pdhg_lambda_max(nullptr, nullptr, KP_PRECOND_NONE, 30, &lm, nullptr), KP_ERR_INVALID_ARG,
            "lambda_max NULL plan");
     expect(pdhg_solve(nullptr, p, nullptr, KP_PRECOND_NONE, &op, p, nullptr, nullptr), KP_ERR_INVALID_ARG,

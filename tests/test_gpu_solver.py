@@ -201,6 +201,10 @@ def test_pdhg_invalid_options():
         with pytest.raises(kp.KpError) as ei:
             kp.pdhg_solve(plan, yt, None, **kw)
         assert ei.value.code == kp._lib.KP_ERR_INVALID_ARG
+    # an unknown preconditioner kind
+    with pytest.raises(kp.KpError) as ei:
+        kp.precond_build(plan, 7)
+    assert ei.value.code == kp._lib.KP_ERR_INVALID_ARG
     plan.close()
 
 
