@@ -381,19 +381,20 @@ __global__ void __launch_bounds__(256) k_interp_tile(InterpArgs a, const int4* _
     }
 }
 
-// 3D, width 4, CG coils per block (CG = 4 or 2): the lanes of one group of
-// 4 CG lanes serve one sample (CG coils x the 4 taps along z), so for each of
-// the 16 (x, y) taps a group reads one contiguous run of 4 CG complex values
-// of the halo; rows of one halo line are padded to H2P cells.  The weights of
-// up to kTlBatch samples are computed once per batch into an LDS table, whose
-// rows also take the interpolated values of their sample (each row is read
-// only by its own sample's lanes before they write it); the 4 z-tap partial
-// sums of a coil are added by a two-step DPP row shift.
+// 3D, width 4, CG coils per block (CG = 4 or 2): a group of 2 CG lanes
+// serves one sample, each lane two coils (one 16-byte read per cell) at one
+// of the 4 taps along z, so for each of the 16 (x, y) taps a group reads one
+// contiguous run of 4 CG complex values of the halo; rows of one halo line
+// are padded to H2P cells.  The weights of up to kTlBatch samples are
+// computed once per batch into an LDS table, whose rows also take the
+// interpolated values of their sample (each row is read only by its own
+// sample's lanes before they write it); the 4 z-tap partial sums of a coil
+// are added by a two-step DPP row shift.
 __device__ __forceinline__ float dpp_row_shr4(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
 }
-__device__ __forceinline__ float dpp_row_shr8(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+__device__ __forceinline__ float dpp_row_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_row_shr2(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
@@ -413,7 +414,7 @@ template <int TB0, int TB1, int TB2, int CG>
 __global__ void __launch_bounds__(kTlThreads) k_interp_tl3(InterpArgs a, const int4* __restrict__ items, KbParams kb) {
     static_assert(CG == 2 || CG == 4, "coil groups of 2 or 4");
     constexpr int NP = CG / 2;          // float4 (two coils) per cell
-    constexpr int SPW = 64 / (4 * CG);  // samples per wave
+    constexpr int SPW = 64 / (4 * NP);  // samples per wave
     extern __shared__ float4 tl_smem[];
     const int ncg = a.C / CG;
     // The coil groups of one piece are launched 8 blocks apart (blocks are
@@ -489,7 +490,7 @@ __global__ void __launch_bounds__(kTlThreads) k_interp_tl3(InterpArgs a, const i
     }
 
     const int lane = tid & 63, wave = tid >> 6;
-    const int c = lane % CG, t2 = (lane / CG) & 3, sub = lane / (4 * CG);
+    const int pr = lane % NP, t2 = (lane / NP) & 3, sub = lane / (4 * NP);
     // halo offsets (in float2) of the 16 (x, y) taps relative to a sample's base
     int toff[16];
 #pragma unroll
@@ -540,7 +541,7 @@ __global__ void __launch_bounds__(kTlThreads) k_interp_tl3(InterpArgs a, const i
             }
         }
         __syncthreads();
-        // ---- one sample per group of 4 CG lanes
+        // ---- one sample per group of 4 NP lanes (two coils per lane)
         for (int i = wave * SPW + sub; i < nbt; i += (kTlThreads / 64) * SPW) {
             float* row = tab + i * 16;
             const float4 w0 = *reinterpret_cast<const float4*>(row);
@@ -549,37 +550,43 @@ __global__ void __launch_bounds__(kTlThreads) k_interp_tl3(InterpArgs a, const i
             const int base = __float_as_int(row[12]);
             const float w0v[4] = {w0.x, w0.y, w0.z, w0.w};
             const float w1v[4] = {w1.x * w2, w1.y * w2, w1.z * w2, w1.w * w2};
-            const int hb = (base + t2) * CG + c;
-            float2 hvv[16];  // all 16 reads issued before the first use
+            const int hb = (base + t2) * CG + 2 * pr;
+            float4 hvv[16];  // all 16 reads issued before the first use
 #pragma unroll
-            for (int t = 0; t < 16; ++t) hvv[t] = halo[hb + toff[t]];
+            for (int t = 0; t < 16; ++t) hvv[t] = *reinterpret_cast<const float4*>(halo + hb + toff[t]);
             // axis-1 taps first, then the axis-0 weight once per t0
-            float ax = 0.f, ay = 0.f;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
             for (int t0 = 0; t0 < 4; ++t0) {
-                float sx = w1v[0] * hvv[t0 * 4].x, sy = w1v[0] * hvv[t0 * 4].y;
+                float s0 = w1v[0] * hvv[t0 * 4].x, s1 = w1v[0] * hvv[t0 * 4].y;
+                float s2 = w1v[0] * hvv[t0 * 4].z, s3 = w1v[0] * hvv[t0 * 4].w;
 #pragma unroll
                 for (int t1 = 1; t1 < 4; ++t1) {
-                    sx = fmaf(w1v[t1], hvv[t0 * 4 + t1].x, sx);
-                    sy = fmaf(w1v[t1], hvv[t0 * 4 + t1].y, sy);
+                    s0 = fmaf(w1v[t1], hvv[t0 * 4 + t1].x, s0);
+                    s1 = fmaf(w1v[t1], hvv[t0 * 4 + t1].y, s1);
+                    s2 = fmaf(w1v[t1], hvv[t0 * 4 + t1].z, s2);
+                    s3 = fmaf(w1v[t1], hvv[t0 * 4 + t1].w, s3);
                 }
-                ax = fmaf(w0v[t0], sx, ax);
-                ay = fmaf(w0v[t0], sy, ay);
+                a0 = fmaf(w0v[t0], s0, a0);
+                a1 = fmaf(w0v[t0], s1, a1);
+                a2 = fmaf(w0v[t0], s2, a2);
+                a3 = fmaf(w0v[t0], s3, a3);
             }
-            if (CG == 4) {
-                ax += dpp_row_shr4(ax);
-                ay += dpp_row_shr4(ay);
-                ax += dpp_row_shr8(ax);
-                ay += dpp_row_shr8(ay);
-            } else {
-                ax += dpp_row_shr2(ax);
-                ay += dpp_row_shr2(ay);
-                ax += dpp_row_shr4(ax);
-                ay += dpp_row_shr4(ay);
+            // the 4 z-tap lanes of a coil pair sit NP lanes apart
+            float acc[4] = {a0, a1, a2, a3};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (NP == 2) {
+                    acc[q] += dpp_row_shr2(acc[q]);
+                    acc[q] += dpp_row_shr4(acc[q]);
+                } else {
+                    acc[q] += dpp_row_shr1(acc[q]);
+                    acc[q] += dpp_row_shr2(acc[q]);
+                }
             }
             // the row's reads above are done (their values fed the sums), so
             // its first CG complex slots take the result
-            if (t2 == 3) reinterpret_cast<float2*>(row)[c] = make_float2(ax, ay);
+            if (t2 == 3) reinterpret_cast<float4*>(row)[pr] = make_float4(acc[0], acc[1], acc[2], acc[3]);
         }
         __syncthreads();
         // ---- output stage of the batch: one sample's CG coils per thread
