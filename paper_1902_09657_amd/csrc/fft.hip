@@ -773,10 +773,12 @@ static int fixed_threads(int nc) { return nc == 12 ? 384 : ((nc == 8 || nc == 16
 // (one phase of the slices of a batch): pass s owns the blocks
 // blk_start[s] .. blk_start[s+1]-1 (passes sorted by length).  Each length
 // has its own column block: the coil block of the passes along the coils
-// (MAP > 0), else kMixCols(L), chosen so that every length needs at most
-// about 43 KB of LDS (three resident blocks per CU); LDS is sized for the
-// largest of them.
-__host__ __device__ constexpr int kMixCols(int L) { return L <= 206 ? 32 : (L <= 320 ? 16 : 8); }
+// (MAP > 0), else kMixCols(L): 32 columns (256 contiguous bytes of every
+// row) up to length 256 and 16 above, so that every length needs at most
+// 68 KB of LDS (two resident blocks per CU); LDS is sized for the largest of
+// them.  With many slices in flight the wider rows pay more than a third
+// resident block would (the 2D axis-0 passes read rows tens of KB apart).
+__host__ __device__ constexpr int kMixCols(int L) { return L <= 256 ? 32 : 16; }
 
 template <int NT, int MAP, int L>
 __device__ __forceinline__ void mixed_body(const FftPass& p, int64_t bid, float2* buf) {
