@@ -765,9 +765,11 @@ __global__ void __launch_bounds__(N1 * NC) k_fft_reg(FftPass p) {
 
 // Column blocks of the specialised kernels: NC columns over NT threads with
 // NT a multiple of NC (8, 16 or 32 columns on 256 threads; 12 columns, one
-// 12-coil row, on 384 threads: 8-10 % faster than 192 on the 2D 12-coil
-// lines).  32 columns = 256 contiguous bytes per row.
-static int fixed_threads(int nc) { return nc == 12 ? 384 : ((nc == 8 || nc == 16 || nc == 32) ? 256 : 0); }
+// 12-coil row, on 768 threads: on the 2D 12-coil lines 384 threads were
+// 8-10 % faster than 192, and 768 a further 1-2 % (plain) to 4-6 % (batched)
+// faster than 384; 960 were slower).  32 columns = 256 contiguous bytes per
+// row.
+static int fixed_threads(int nc) { return nc == 12 ? 768 : ((nc == 8 || nc == 16 || nc == 32) ? 256 : 0); }
 
 // One launch over the passes of many independent transforms of mixed lengths
 // (one phase of the slices of a batch): pass s owns the blocks
@@ -817,7 +819,7 @@ static const void* mixed_kernel(int map, int* nt) {
     switch (map) {
         case 0: *nt = 512; return (const void*)k_fft_batch_mixed<512, 0>;
         case 8: *nt = 256; return (const void*)k_fft_batch_mixed<256, 8>;
-        case 12: *nt = 384; return (const void*)k_fft_batch_mixed<384, 12>;
+        case 12: *nt = 768; return (const void*)k_fft_batch_mixed<768, 12>;
         case 16: *nt = 512; return (const void*)k_fft_batch_mixed<512, 16>;
         default: return nullptr;
     }
@@ -842,7 +844,7 @@ void launch_fft_batch_mixed(const FftPass* d_passes, const int64_t* d_blk_start,
     else if (map == 8)
         hipLaunchKernelGGL((k_fft_batch_mixed<256, 8>), g, dim3(256), lds, s, d_passes, d_blk_start, n);
     else if (map == 12)
-        hipLaunchKernelGGL((k_fft_batch_mixed<384, 12>), g, dim3(384), lds, s, d_passes, d_blk_start, n);
+        hipLaunchKernelGGL((k_fft_batch_mixed<768, 12>), g, dim3(768), lds, s, d_passes, d_blk_start, n);
     else
         hipLaunchKernelGGL((k_fft_batch_mixed<512, 16>), g, dim3(512), lds, s, d_passes, d_blk_start, n);
     KP_LAUNCH_CHECK();
@@ -935,7 +937,7 @@ static bool launch_fixed(const FftPass& p, hipStream_t s, int lim) {
     fft_kernel_t fn = nc == 32   ? fixed_for<32, 256>(p.L)
                       : nc == 16 ? fixed_for<16, 256>(p.L)
                       : nc == 8  ? fixed_for<8, 256>(p.L)
-                                 : fixed_for<12, 384>(p.L);
+                                 : fixed_for<12, 768>(p.L);
     if (!fn) return false;
     const size_t lds = sizeof(float2) * (size_t)p.L * (nc + 1);
     if (lds > (size_t)lim) return false;
@@ -955,7 +957,7 @@ bool fft_fixed_ok(int L, int nc) {
     const int nt = fixed_threads(nc);
     if (nt == 0) return false;
     fft_kernel_t fn = nc == 32 ? fixed_for<32, 256>(L) : nc == 16 ? fixed_for<16, 256>(L)
-                    : nc == 8 ? fixed_for<8, 256>(L) : fixed_for<12, 384>(L);
+                    : nc == 8 ? fixed_for<8, 256>(L) : fixed_for<12, 768>(L);
     return fn && sizeof(float2) * (size_t)L * (nc + 1) <= (size_t)lds_limit();
 }
 
