@@ -58,13 +58,16 @@ def plain_solve(kp, sh, k, maps, y, p, alpha, W, bin_size=None, max_chunk=0, spr
 
 # grid lengths 160, 200, 240: the one-launch-per-phase path
 FAST = dict(sizes=[128, 160, 192, 128], spokes=[40, 24, 33, 64])
+# grid lengths 320 and 400 (the narrower column blocks of the long lengths)
+LONG = dict(sizes=[256, 320, 128], spokes=[20, 16, 30])
 
 
-@pytest.mark.parametrize("C", [4, 12])
-def test_batch_fast_equals_plain(C):
+@pytest.mark.parametrize("C,sizes", [(4, "FAST"), (8, "FAST"), (12, "FAST"), (16, "FAST"), (8, "LONG"), (12, "LONG")])
+def test_batch_fast_equals_plain(C, sizes):
     kp = _kp()
-    print("batch fast C", C, flush=True)
-    sl = slices(FAST["sizes"], FAST["spokes"], C, 11)
+    print("batch fast C", C, sizes, flush=True)
+    cfg = FAST if sizes == "FAST" else LONG
+    sl = slices(cfg["sizes"], cfg["spokes"], C, 11)
     b = make_batch(kp, sl, tune=False)
     assert all(kp.nufft_batch_info(b, i)["fast"] for i in range(len(b)))
     ps = []
