@@ -65,8 +65,9 @@ CASES = [
     # 3D, coils in groups of four (the tap-lane interpolation)
     ((24, 32, 40), 4, 6000, 1.25, 4),
     ((40, 36, 44), 8, 30000, 1.25, 4),
-    # three coil groups per piece (blocks dealt to (piece, group) pairs)
+    # three and four coil groups per piece (blocks dealt to (piece, group) pairs)
     ((24, 24, 32), 12, 5000, 1.25, 4),
+    ((16, 24, 24), 16, 3000, 1.25, 4),
 ]
 
 
