@@ -125,6 +125,8 @@ SOLVE_CASES = [
     ((16, 20, 16), 2, 3000, 1.25, 4, "l2", 1e-2, "none", 10, 2),
     ((16, 24, 16), 4, 5000, 1.25, 4, "l2", 1e-3, "mc", 10, 2),
     ((16, 16, 32), 8, 6000, 1.25, 4, "l1wav", 5e-3, "sc", 8, 2),
+    # three coil groups in the fused dual update of the 3D interpolation
+    ((16, 16, 24), 12, 3000, 1.25, 4, "l1wav", 5e-3, "mc", 6, 2),
     # deepest wavelet levels with axes shorter than the filter (L = 2, 4, 6)
     ((16, 24), 2, 1500, 1.25, 4, "l1wav", 5e-3, "sc", 8, 3),
     ((8, 16, 12), 2, 2000, 1.25, 4, "l1wav", 5e-3, "none", 6, 2),
